@@ -1,0 +1,268 @@
+"""Pins of the oracle against facts that do not come from the oracle itself:
+gate identities, brute-force dense matrices, norms, Porter-Thomas moments,
+the closed forms of Eq. 1-3 and Appendix A, and brute-force sorting.
+CPU only.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import sv, tn, topk
+
+pytestmark = pytest.mark.usefixtures("oracle_built")
+
+PAULI_X = np.array([[0, 1], [1, 0]], np.complex128)
+PAULI_Y = np.array([[0, -1j], [1j, 0]], np.complex128)
+PAULI_W = (PAULI_X + PAULI_Y) / math.sqrt(2)
+
+
+# ---------------------------------------------------------------- gates (Fig. 1)
+@pytest.mark.parametrize("g,p", [(wl.SQRT_X, PAULI_X), (wl.SQRT_Y, PAULI_Y),
+                                 (wl.SQRT_W, PAULI_W)])
+def test_sqrt_gates_square_to_pauli(g, p):
+    assert np.abs(g.conj().T @ g - np.eye(2)).max() < 1e-15
+    # exp(-i pi/4 P)^2 = exp(-i pi/2 P) = -i P
+    assert np.abs(g @ g - (-1j) * p).max() < 1e-15
+
+
+def test_fsim_identities():
+    f = wl.fsim(math.pi / 2, 0.0)
+    e01 = np.zeros(4, complex); e01[1] = 1
+    e10 = np.zeros(4, complex); e10[2] = 1
+    assert np.abs(f @ e01 - (-1j) * e10).max() < 1e-15
+    phi = 0.37
+    assert np.abs(wl.fsim(0.0, phi) - np.diag([1, 1, 1, np.exp(-1j * phi)])).max() < 1e-15
+    g = wl.FSIM_DEFAULT
+    assert np.abs(g.conj().T @ g - np.eye(4)).max() < 1e-15
+    swap = np.eye(4)[[0, 2, 1, 3]]
+    assert np.abs(swap @ g @ swap - g).max() < 1e-15  # symmetric under qubit swap
+
+
+# ------------------------------------------------------ SV vs dense brute force
+def _dense_1q(n, q, g):
+    out = np.zeros((1 << n, 1 << n), complex)
+    for i in range(1 << n):
+        for k in range(1 << n):
+            if (i ^ k) & ~(1 << q):
+                continue
+            out[i, k] = g[(i >> q) & 1, (k >> q) & 1]
+    return out
+
+
+def _dense_2q(n, q0, q1, g):
+    out = np.zeros((1 << n, 1 << n), complex)
+    mask = (1 << q0) | (1 << q1)
+    for i in range(1 << n):
+        for k in range(1 << n):
+            if (i ^ k) & ~mask:
+                continue
+            r = 2 * ((i >> q0) & 1) + ((i >> q1) & 1)
+            c = 2 * ((k >> q0) & 1) + ((k >> q1) & 1)
+            out[i, k] = g[r, c]
+    return out
+
+
+def test_sv_1q_matches_dense():
+    for n in range(1, 5):
+        for q in range(n):
+            g = wl.random_complex((2, 2), seed=100 + 10 * n + q)
+            psi = wl.random_complex(1 << n, seed=7 + n + q)
+            ref = _dense_1q(n, q, g) @ psi
+            sv.apply_1q(psi, q, g)
+            assert np.abs(psi - ref).max() < 1e-13
+
+
+def test_sv_2q_matches_dense():
+    for n in range(2, 5):
+        for q0 in range(n):
+            for q1 in range(n):
+                if q0 == q1:
+                    continue
+                g = wl.random_complex((4, 4), seed=200 + 16 * n + 4 * q0 + q1)
+                psi = wl.random_complex(1 << n, seed=9 + n + q0 * 5 + q1)
+                ref = _dense_2q(n, q0, q1, g) @ psi
+                sv.apply_2q(psi, q0, q1, g)
+                assert np.abs(psi - ref).max() < 1e-13
+
+
+def _dense_run(circ, projectors=()):
+    """Full circuit by explicit 2^n x 2^n matrices, projectors as dense matrices."""
+    n = circ.n_qubits
+    psi = np.zeros(1 << n, complex)
+    psi[0] = 1
+    count = [0] * n
+    for g in circ.gates:
+        if len(g.qubits) == 1:
+            psi = _dense_1q(n, g.qubits[0], g.matrix) @ psi
+        else:
+            for (q, j, v) in projectors:
+                if q in g.qubits and count[q] == j:
+                    proj = np.diag([1.0 if ((i >> q) & 1) == v else 0.0
+                                    for i in range(1 << n)])
+                    psi = proj @ psi
+            psi = _dense_2q(n, g.qubits[0], g.qubits[1], g.matrix) @ psi
+            for q in g.qubits:
+                count[q] += 1
+    return psi
+
+
+def test_whole_circuit_and_projectors_match_dense():
+    circ = wl.random_circuit(2, 2, 6, seed=3)
+    psi = sv.run(circ)
+    assert np.abs(psi - _dense_run(circ)).max() < 1e-13
+    projs = [(0, 1, 1), (3, 2, 0), (1, 1, 0)]
+    psi_p = sv.run(circ, projs)
+    assert np.abs(psi_p - _dense_run(circ, projs)).max() < 1e-13
+    assert sv.norm2(psi_p) < 1.0 - 1e-3  # a projector removes weight
+
+
+def test_unit_norm_after_every_layer():
+    circ = wl.random_circuit(3, 4, 8, seed=wl.CIRCUIT_SEED)
+    ends = [i + 1 for i in range(len(circ.gates) - 1)
+            if circ.gates[i + 1].cycle != circ.gates[i].cycle]
+    ends.append(len(circ.gates))
+    for e in ends:
+        psi = sv.run(circ, stop_after_gate=e)
+        assert abs(sv.norm2(psi) - 1.0) < 1e-10
+
+
+# --------------------------------------------- Porter-Thomas and XEB (Eq. 1-2)
+@pytest.fixture(scope="module")
+def deep20():
+    circ = wl.random_circuit(4, 5, 16, seed=11)
+    return circ, sv.run(circ)
+
+
+def test_porter_thomas_moments(deep20):
+    _, psi = deep20
+    N = psi.size
+    m2, m3 = sv.moments(psi)
+    assert abs(N * m2 - 2.0) < 0.1      # E[(Nq)^2] = 2 under P(Nq) = e^{-Nq}
+    assert abs(N * N * m3 - 6.0) < 0.6  # E[(Nq)^3] = 6
+
+
+def test_exact_sampling_xeb_is_one(deep20):
+    _, psi = deep20
+    N = psi.size
+    m2, _ = sv.moments(psi)
+    expected = N * m2 - 1.0              # E[XEB] under exact sampling, from q
+    M = 100_000
+    s = sv.sample_exact(psi, M, seed=5)
+    q = topk.probabilities(psi[s.astype(np.int64)])
+    x = topk.xeb(q, 20)
+    sigma = math.sqrt(2.0 / M)
+    assert abs(x - expected) < 5 * sigma
+    assert abs(x - 1.0) < 0.1
+
+
+def test_global_topk_xeb_matches_appendix_a(deep20):
+    """Ideal top-k over all 2^20 strings: XEB -> ln(N/k) (Eq. 2)."""
+    _, psi = deep20
+    k = 1024
+    idx, _ = topk.topk(psi, psi.size, k)
+    q = topk.probabilities(psi[idx[0]])
+    x = topk.xeb(q, 20)
+    assert abs(x - topk.expected_topk_xeb(psi.size, k)) < 0.2
+    assert abs(topk.porter_thomas_topk_xeb(psi.size, k) - 10 * math.log(2)) < 1e-12
+    assert abs(topk.expected_topk_xeb(psi.size, k) - math.log(1024)) < 1e-3
+
+
+def test_per_group_top1_xeb():
+    """Per group of 64 correlated strings, top-1: E[XEB] = H_64 - 1 = 3.744."""
+    circ = wl.random_circuit(4, 5, 16, seed=12)
+    openq = list(range(14, 20))
+    cb = wl.closed_bitstrings(20, openq, 256, seed=4)
+    a = sv.group_amplitudes(circ, openq, cb)
+    idx, _ = topk.topk(a, 64, 1)
+    q = topk.probabilities(a[np.arange(256), idx[:, 0]])
+    x = topk.xeb(q, 20)
+    assert abs(topk.expected_topk_xeb(64, 1) - 3.7439) < 1e-3
+    assert abs(x - 3.744) < 4 * 0.08 + 0.05
+
+
+def test_paper_topk_amplification_value():
+    """Paper: k = 2^15 of 2^30 gives ln 2^15 = 10.3972 (Methods B)."""
+    assert abs(topk.porter_thomas_topk_xeb(2 ** 30, 2 ** 15) - 10.3972) < 1e-4
+    assert abs(topk.expected_topk_xeb(2 ** 30, 2 ** 15) - 10.3972) < 1e-3
+
+
+# ------------------------------------------------------------------ top-k sort
+def test_topk_matches_bruteforce_with_ties():
+    rng = np.random.Generator(np.random.PCG64(3))
+    a = (rng.integers(0, 4, 512) + 1j * rng.integers(0, 3, 512)).astype(np.complex128)
+    for gs, k in ((64, 1), (64, 5), (128, 17), (512, 512)):
+        i1, p1 = topk.topk(a, gs, k)
+        i2, p2 = topk.topk_bruteforce(a, gs, k)
+        assert np.array_equal(i1, i2)
+        assert np.array_equal(p1, p2)
+
+
+def test_probability_has_no_fused_rounding():
+    # 1 + 2^-30 squared: exact square needs 61 bits; rounded product then sum
+    x = 1.0 + 2.0 ** -30
+    a = np.array([x + 1j * x])
+    p = topk.probabilities(a)[0]
+    assert p == (x * x) + (x * x)
+
+
+# ------------------------------------------------- TN oracle vs SV (Methods C)
+def test_tn_equals_sv_and_slicing_identity():
+    circ = wl.random_circuit(3, 3, 8, seed=21)
+    openq = [6, 7, 8]
+    cb = wl.closed_bitstrings(9, openq, 8, seed=2)
+    exact = sv.group_amplitudes(circ, openq, cb)
+    full = tn.amplitudes(circ, openq, cb)
+    assert np.abs(full - exact).max() < 1e-13
+    wires = tn.wire_list(tn.canonical_network(circ, openq, cb))
+    chosen = [wires[3], wires[7], wires[11], wires[15]]
+    total = np.zeros_like(exact)
+    for s in range(16):
+        v = tn.slice_values(s, 4)
+        a_tn = tn.amplitudes(circ, openq, cb, chosen, v)
+        a_sv = sv.group_amplitudes(circ, openq, cb,
+                                   [(q, j, x) for (q, j), x in zip(chosen, v)])
+        assert np.abs(a_tn - a_sv).max() < 1e-13
+        total += a_tn
+    assert np.abs(total - exact).max() < 1e-13
+    # a prefix [0, 2^(S-D)) fixes the D most significant sliced wires to 0
+    prefix = sum(tn.amplitudes(circ, openq, cb, chosen, tn.slice_values(s, 4))
+                 for s in range(4))
+    proj = sv.group_amplitudes(circ, openq, cb, [(chosen[2][0], chosen[2][1], 0),
+                                                 (chosen[3][0], chosen[3][1], 0)])
+    assert np.abs(prefix - proj).max() < 1e-13
+
+
+def test_tn_tree_validation():
+    circ = wl.random_circuit(2, 2, 4, seed=1)
+    leaves = tn.canonical_network(circ, [0, 1, 2, 3], [0])
+    keep = tn._keep_labels([0, 1, 2, 3])
+    steps, base = tn.greedy_steps(leaves, keep)
+    tn.contract_tree(leaves, steps, base, keep)
+    bad = list(steps)
+    bad[-1] = (bad[-1][0], bad[-1][0])
+    with pytest.raises(ValueError):
+        tn.contract_tree(leaves, bad, base, keep)
+    with pytest.raises(ValueError):
+        tn.contract_tree(leaves, steps[:-1], base, keep)
+
+
+def test_partial_sum_fidelity_tracks_fraction():
+    """Eq. 3: contracting a fraction f = 2^-D of the sub-networks gives
+    fidelity close to f."""
+    circ = wl.random_circuit(4, 5, 14, seed=31)
+    psi = sv.run(circ)
+    leaves_wires = tn.wire_list(tn.canonical_network(circ, list(range(20)), [0]))
+    mid = [w for w in leaves_wires if 2 <= w[1] <= 4]
+    rng = np.random.Generator(np.random.PCG64(8))
+    for D in (1, 2, 3):
+        fids = []
+        for rep in range(3):
+            pick = rng.choice(len(mid), size=D, replace=False)
+            projs = [(mid[i][0], mid[i][1], 0) for i in pick]
+            psi_d = sv.run(circ, projs)
+            ov = abs(np.vdot(psi, psi_d)) ** 2 / (sv.norm2(psi) * sv.norm2(psi_d))
+            fids.append(ov)
+        assert abs(np.mean(fids) / 2.0 ** -D - 1.0) < 0.3
