@@ -1,0 +1,177 @@
+"""Benchmark: sliced-subtask contractions per second on one MI355X.
+
+A step contracts one chunk of slices of the workload into a float64
+amplitude accumulator and runs the top-k post-selection on it (the whole hot
+path).  Inputs (plan, leaves, workspace) are resident in HBM before timing.
+Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rqc30|rqc53]
+                  [--dtype chalf|c64] [--slices-per-step S]
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MI355X = {"hbm_gbs": 8000.0, "fp16_tflops": 2500.0, "fp32_tflops": 157.3}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rqc30")
+    ap.add_argument("--dtype", default="c64")
+    ap.add_argument("--slices-per-step", type=int, default=16)
+    ap.add_argument("--launch", default="stream")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(plan, circ, openq, cb, seconds):
+    """The oracle's complex128 contraction of slice 0 along the plan's tree,
+    run for about `seconds` of host time; the fraction of the slice's
+    multiply-adds done per second is reported as slices/s."""
+    import numpy as np
+    from oracle import tn
+
+    leaf_canon, steps, base = plan.tree()
+    wires = plan.sliced_wires()
+    dims, macs, _ = plan.steps()
+    t0 = time.time()
+    leaves = tn.canonical_network(circ, openq, cb)
+    if wires:
+        leaves = tn.fix_wires(leaves, wires, tn.slice_values(0, len(wires)))
+    keep = tn._keep_labels(openq)
+    nodes = dict(leaves)
+    done = 0.0
+    n_done = 0
+    t_start = time.time()
+    for i, (a, b) in enumerate(steps):
+        la, A = nodes.pop(a)
+        lb, B = nodes.pop(b)
+        nodes[base + i] = tn.contract_pair(la, A, lb, B, keep)
+        done += macs[i]
+        n_done += 1
+        if time.time() - t_start > seconds:
+            break
+    el = time.time() - t_start
+    per_slice = float(macs.sum())
+    frac = done / per_slice
+    return {"value": frac / el, "unit": "slices/s", "cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle",
+            "sample": f"complex128 numpy contraction of slice 0 along the plan's tree, "
+                      f"{n_done}/{len(steps)} steps = {frac:.3g} of the slice's multiply-adds "
+                      f"in {el:.1f} s (network build {t_start - t0:.1f} s excluded)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2406_18889_amd as lf
+    import workloads as wl
+
+    torch.cuda.set_device(0)
+    circ, openq, cb, spec = wl.standard_workload(args.workload)
+    kw = {}
+    if args.workload == "rqc30":
+        from tests.golden.make_rqc30 import RQC30_SLICED_WIRES
+        kw["sliced_wires"] = RQC30_SLICED_WIRES
+    plan = lf.Plan(circ, openq, cb, dtype=args.dtype, max_log2=spec["max_log2"],
+                   launch=args.launch, check_overflow=False, **kw)
+    info = plan.info()
+    plan.bind()
+    n_slices = info["n_slices"]
+    S = min(args.slices_per_step, n_slices)
+    amps = plan.new_amplitudes()
+    stream = torch.cuda.current_stream()
+
+    # calibrate / invariant part outside the timed region
+    plan.contract(0, 1, amps)
+    torch.cuda.synchronize()
+
+    def step(i):
+        s0 = (i * S) % n_slices
+        s1 = min(s0 + S, n_slices)
+        plan.contract(s0, s1, amps)
+        lf.postselect_topk(amps, 1 << len(openq), 1)
+        return s1 - s0
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    for i in range(args.steps):
+        done += step(args.warmup + i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = done / dt
+
+    # per-step kernel timing (HIP events on the plan's stream) -> dominant step
+    ms = plan.profile_steps(reps=3)
+    dims, macs, byts = plan.steps()
+    var = dims[:, 4] == 1
+    share = np.where(var, ms, 0.0)
+    dom = int(np.argmax(share))
+    flops = 8.0 * macs[dom]
+    ai = flops / byts[dom]
+    half = dims[dom, 5] == 1
+    peak_tf = MI355X["fp16_tflops"] if half else MI355X["fp32_tflops"]
+    ridge = peak_tf * 1e12 / (MI355X["hbm_gbs"] * 1e9)
+    t = ms[dom] * 1e-3
+    if ai >= ridge:
+        roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": peak_tf, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": byts[dom] / t / 1e9, "peak": MI355X["hbm_gbs"], "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = {"step": dom, "nz_nm_nn_nk": [int(x) for x in dims[dom, :4]],
+                      "kind": "mfma" if dims[dom, 7] == 1 else "thin",
+                      "ms": float(ms[dom]), "share_of_slice": float(share[dom] / share.sum())}
+
+    per_slice_flops = 8.0 * info["macs_per_slice"]
+    out = {
+        "metric": "sliced-subtask contractions/s",
+        "value": value,
+        "unit": "slices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "chalf" if args.dtype == "chalf" else "c64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "qubits": circ.n_qubits, "cycles": spec["cycles"],
+                   "open_qubits": len(openq), "closed_strings": len(cb),
+                   "slices_total": n_slices, "slices_per_step": S,
+                   "max_log2_intermediate": info["max_log2_intermediate"]},
+        "algorithmic_tflops": value * per_slice_flops / 1e12,
+        "mfma_frac_algorithmic": value * per_slice_flops / 1e12 /
+                                  (MI355X["fp16_tflops"] if args.dtype == "chalf" else MI355X["fp32_tflops"]),
+        "macs_per_slice": info["macs_per_slice"],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(plan, circ, openq, cb, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

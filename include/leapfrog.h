@@ -1,0 +1,226 @@
+/*
+ * leapfrog.h - C ABI of the sliced tensor-network amplitude library for
+ * MI355X (gfx950).
+ *
+ * The method (arXiv 2406.18889, Methods A and C): the amplitudes of a random
+ * quantum circuit for k groups of 2^l correlated bitstrings (l open output
+ * qubits take all values; the other qubits are fixed to k sampled closed
+ * strings) are computed by contracting the circuit's tensor network.  The
+ * network is sliced: a set of S wires is fixed to each of its 2^S value
+ * combinations, every combination (a slice, or sub-network) is contracted
+ * independently, and the network's value is the sum over all slices
+ * (slicing identity, Methods C).  Summing only a fraction f of the slices
+ * gives an approximation whose fidelity is close to f (Eq. 3).  The top-k
+ * step (Methods A and B, Eq. 2, Appendix A) then keeps, per group or over
+ * all groups, the k strings with the largest |amplitude|^2.
+ *
+ * Conventions
+ *  - Basis: qubit 0 is the least significant bit of a basis index.  A
+ *    two-qubit gate matrix is indexed by 2*bit(q[0]) + bit(q[1]); row =
+ *    output.  Matrices are complex128, row-major, (re, im) interleaved.
+ *  - Output amplitudes: out[b * 2^l + j] is the amplitude of closed string b
+ *    with bit open_qubits[i] of the result equal to bit i of j.
+ *  - A wire (q, j), 1 <= j < number of two-qubit gates on q, is the point
+ *    on qubit q immediately before its j-th (0-based) two-qubit gate, after
+ *    the single-qubit gates that precede it.  Sliced wire t takes bit t of
+ *    the slice number, so the slice prefix [0, 2^(S-D)) fixes the D
+ *    last-listed sliced wires to 0.
+ *  - Every call returns an lf_status; 0 is success.  No exception crosses
+ *    the boundary.  lf_last_error() returns a thread-local message for the
+ *    last failing call on the calling thread.
+ *  - Device pointers are HIP device addresses owned by the caller; `stream`
+ *    is a hipStream_t (NULL = the default stream).  Calls that take a stream
+ *    are asynchronous on it unless stated otherwise.
+ */
+#ifndef LEAPFROG_H
+#define LEAPFROG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lf_status;
+enum {
+  LF_OK = 0,
+  LF_INVALID_ARGUMENT = 1, /* malformed circuit, qubit list, range or size */
+  LF_PLAN_INFEASIBLE = 2,  /* no tree fits the cap within 64 sliced wires */
+  LF_OUT_OF_WORKSPACE = 3, /* bound workspace smaller than required */
+  LF_HIP_ERROR = 4,        /* a HIP runtime call failed */
+  LF_OVERFLOW = 5,         /* complex-half saturation in the contracted range */
+  LF_NOT_BOUND = 6,        /* contraction before lf_plan_bind_workspace */
+  LF_INTERNAL = 7
+};
+
+enum { LF_C64 = 0, LF_CHALF = 1 };          /* contraction arithmetic */
+enum { LF_COST_FLOPMEM = 0, LF_COST_MLP = 1 }; /* path-search cost model */
+enum { LF_LAUNCH_STREAM = 0, LF_LAUNCH_GRAPH = 1 };
+
+typedef struct lf_gate {
+  int32_t n_q;       /* 1 or 2 */
+  int32_t q[2];      /* qubits; q[1] unused for n_q == 1 */
+  int32_t layer;     /* cycle index (informational) */
+  double mat[32];    /* (re, im) pairs, row-major 2x2 (first 8) or 4x4 */
+} lf_gate;
+
+typedef struct lf_circuit {
+  int32_t n_qubits;  /* 1..63 */
+  int32_t n_gates;
+  const lf_gate* gates; /* in time order */
+} lf_circuit;
+
+typedef struct lf_plan_opts {
+  int32_t dtype;                 /* LF_C64 or LF_CHALF */
+  int32_t max_log2_intermediate; /* cap M: every sliced intermediate <= 2^M elements */
+  int32_t n_sliced_wires;        /* -1: as many as the cap needs; >= 0: at least this many */
+  const int32_t* sliced_wires;   /* optional forced wires, pairs (q, j), bit order; NULL = planner */
+  int32_t n_forced;              /* number of pairs in sliced_wires */
+  int32_t cost_model;            /* LF_COST_FLOPMEM or LF_COST_MLP (needs a loaded model) */
+  int32_t greedy_trials;         /* randomized greedy trees tried */
+  int32_t partition_trials;      /* recursive min-cut bisection trees tried */
+  int64_t sa_iters;              /* annealing moves over the best tree (0 = none) */
+  uint64_t seed;                 /* search seed */
+  int32_t chalf_min_log2;        /* complex-half only: steps touching a tensor of at
+                                    least 2^this elements run in half, smaller ones in
+                                    complex64 */
+  int32_t launch_mode;           /* LF_LAUNCH_STREAM or LF_LAUNCH_GRAPH */
+  int32_t check_overflow;        /* nonzero: lf_contract_slices synchronizes at its end
+                                    and reports LF_OVERFLOW on saturation */
+  int32_t slices_per_graph;      /* graph mode: slices captured per graph replay */
+} lf_plan_opts;
+
+typedef struct lf_plan_info {
+  int64_t n_slices;              /* 2^S */
+  int32_t n_sliced_wires;        /* S */
+  int32_t n_steps;               /* pairwise contractions */
+  int32_t n_variant_steps;       /* steps that depend on the slice */
+  int32_t n_leaves;
+  int32_t max_log2_intermediate; /* largest tensor of one slice, log2 elements */
+  int32_t dtype;
+  int32_t n_open;
+  int64_t n_batch;
+  int32_t n_batch_log2;          /* batch padded to 2^this */
+  int32_t n_half_steps;          /* steps computed in complex-half */
+  double macs_per_slice;         /* complex multiply-adds of the slice-dependent steps */
+  double macs_invariant;         /* once per plan: slice-independent subtrees */
+  double bytes_per_slice;        /* operand + result bytes of the slice-dependent steps */
+  double bytes_invariant;
+  double log2_total_macs;        /* all slices */
+  uint64_t workspace_bytes;      /* device bytes lf_plan_bind_workspace needs */
+  int32_t leaf_id_base;          /* first node id of an intermediate in lf_plan_tree */
+} lf_plan_info;
+
+typedef struct lf_plan lf_plan;
+
+/* Defaults: LF_C64, cap 2^28, planner-chosen slices, FLOP+memory cost,
+ * 8 greedy and 64 partition trials, no annealing, seed 1, chalf_min_log2 16,
+ * stream launch,
+ * overflow check on, 8 slices per graph. */
+void lf_plan_opts_default(lf_plan_opts* opts);
+
+/*
+ * Builds the network of `circuit` with output qubits `open_qubits` (l of
+ * them, l <= 30) and `n_batch` closed strings `closed_bits` (each a full
+ * n-bit mask; bits at open positions are ignored; n_batch <= 2^20, padded
+ * internally to a power of two), folds single-qubit gates in float64,
+ * searches a contraction tree and slicing under the cap (Methods C, D), lays
+ * out every tensor (dimension order, Methods C) and returns an opaque plan
+ * in *out_plan, owned by the caller and freed with lf_plan_destroy.  Host
+ * only; no device call.  Errors: LF_INVALID_ARGUMENT, LF_PLAN_INFEASIBLE.
+ */
+lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits,
+                           int32_t n_open, const uint64_t* closed_bits, int64_t n_batch,
+                           const lf_plan_opts* opts, lf_plan** out_plan);
+
+lf_status lf_plan_get_info(const lf_plan* plan, lf_plan_info* out);
+
+/* Sliced wires as pairs (q, j) in bit order: out_qj[2t], out_qj[2t+1]. */
+lf_status lf_plan_sliced_wires(const lf_plan* plan, int32_t* out_qj);
+
+/*
+ * The contraction tree: leaf_canon[i] is the canonical id of leaf node i
+ * (the k-th two-qubit gate of the circuit is leaf k; a qubit q without a
+ * two-qubit gate is leaf n_2q + q); step s contracts nodes left[s] and
+ * right[s], given as canonical leaf ids or as leaf_id_base + s' for the
+ * result of an earlier step s'.  Steps are in execution order.
+ */
+lf_status lf_plan_tree(const lf_plan* plan, int32_t* leaf_canon, int32_t* left, int32_t* right);
+
+/*
+ * Per-step shape: dims[8s .. 8s+7] = (nz, nm, nn, nk, variant, dtype,
+ * out_dtype, kernel) where the step computes C[z,m,n] = sum_k A[z,m,k] B[z,n,k]
+ * over 2^nz x 2^nm x 2^nn x 2^nk; macs[s], bytes[s] its work.  Either
+ * output pointer except dims may be NULL.
+ */
+lf_status lf_plan_steps(const lf_plan* plan, int32_t* dims, double* macs, double* bytes);
+
+/*
+ * Binds `bytes` of device memory at `dev_ptr` (256-byte aligned, owned by
+ * the caller, at least info.workspace_bytes) and uploads the leaf tensors on
+ * `stream`.  The workspace must stay valid until the plan is destroyed or
+ * rebound.  Errors: LF_OUT_OF_WORKSPACE, LF_INVALID_ARGUMENT, LF_HIP_ERROR.
+ */
+lf_status lf_plan_bind_workspace(lf_plan* plan, void* dev_ptr, uint64_t bytes, void* stream);
+
+/*
+ * Contracts slices [slice_begin, slice_end) and ADDS their sum to
+ * out_amps (device, complex128, [n_batch][2^l], (re, im) interleaved), in
+ * float64, one slice after another in increasing order (deterministic).
+ * The full range gives the exact amplitudes; a prefix gives the fraction f
+ * of Methods A.  begin == end is a no-op.  Asynchronous on `stream` unless
+ * check_overflow is set, in which case it synchronizes and returns
+ * LF_OVERFLOW if any complex-half value saturated.  A plan is used by one
+ * stream at a time.  Errors: LF_NOT_BOUND, LF_INVALID_ARGUMENT,
+ * LF_HIP_ERROR, LF_OVERFLOW.
+ */
+lf_status lf_contract_slices(lf_plan* plan, int64_t slice_begin, int64_t slice_end,
+                             void* out_amps, void* stream);
+
+/*
+ * Top-k post-selection (Methods A): for each of n_groups consecutive groups
+ * of group_size complex128 amplitudes, p = re*re + im*im in float64 (each
+ * product and the sum rounded separately), ordered by p descending then
+ * position ascending; writes the first k positions to out_idx[g*k + r]
+ * (int64, device) and their p to out_prob (float64, device).  group_size =
+ * 2^l gives one selection per closed string; group_size = n_batch * 2^l
+ * selects over all candidates.  Limits: 1 <= k <= min(group_size, 1024),
+ * group_size <= 2^26.  Errors: LF_INVALID_ARGUMENT, LF_HIP_ERROR.
+ */
+lf_status lf_postselect_topk(const void* amps, int64_t n_groups, int64_t group_size, int32_t k,
+                             int64_t* out_idx, double* out_prob, void* stream);
+
+/*
+ * Times every step of slice 0 on `stream` with HIP events (reps runs each,
+ * after one warm-up) and writes the mean milliseconds per step to out_ms
+ * [n_steps].  Synchronous.  Needs a bound workspace.
+ */
+lf_status lf_profile_steps(lf_plan* plan, int32_t reps, double* out_ms, void* stream);
+
+/*
+ * One pairwise complex contraction, the operation every step of a plan
+ * performs (Methods C):  C[z,m,n] = scale * sum_k A[z,m,k] * B[z,n,k]  over
+ * 2^nz x 2^nm x 2^nn x 2^nk.  A is a row-major [2^nz][2^nm][2^nk] array and B
+ * a row-major [2^nz][2^nn][2^nk] array of (re, im) pairs in dtype_in; C
+ * element (z,m,n) is written, in dtype_out, at element offset
+ * sum_b bit_b(z) c_strides[b] + sum_b bit_b(m) c_strides[nz+b] +
+ * sum_b bit_b(n) c_strides[nz+nm+b]; the strides must map distinct (z,m,n)
+ * to distinct elements.  kernel: 0 streaming (narrow side), 1 MFMA tile,
+ * -1 the plan's default choice.  Device pointers owned by the caller; A and
+ * B 16-byte aligned.  Limits: nz <= 20, nm, nn <= 40.  Errors:
+ * LF_INVALID_ARGUMENT, LF_HIP_ERROR.
+ */
+lf_status lf_contract_pair(int32_t dtype_in, int32_t dtype_out, int32_t kernel, const void* A,
+                           const void* B, void* C, int32_t nz, int32_t nm, int32_t nn, int32_t nk,
+                           const int64_t* c_strides, float scale, void* stream);
+
+void lf_plan_destroy(lf_plan* plan);
+
+const char* lf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEAPFROG_H */

@@ -1,0 +1,6 @@
+"""Sliced tensor-network amplitudes of random quantum circuits and top-k
+post-selection (arXiv 2406.18889) on MI355X: a C-ABI HIP library
+(include/leapfrog.h) with a thin Python binding.
+"""
+
+from .api import Plan, build_network, contract_pair, contract_slices, postselect_topk  # noqa: F401

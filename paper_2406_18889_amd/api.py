@@ -1,0 +1,231 @@
+"""Python face of the C-ABI library: the same calls as include/leapfrog.h.
+
+PyTorch supplies device memory (workspace, amplitude and top-k buffers) and
+streams; every computation runs in the library.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import check
+
+DTYPES = {"c64": _lib.LF_C64, "complex64": _lib.LF_C64, "chalf": _lib.LF_CHALF,
+          "complex-half": _lib.LF_CHALF}
+COST = {"flopmem": _lib.LF_COST_FLOPMEM, "mlp": _lib.LF_COST_MLP}
+LAUNCH = {"stream": _lib.LF_LAUNCH_STREAM, "graph": _lib.LF_LAUNCH_GRAPH}
+
+
+def _circuit_struct(circuit):
+    n = len(circuit.gates)
+    arr = (_lib.lf_gate * max(n, 1))()
+    for i, g in enumerate(circuit.gates):
+        arr[i].n_q = len(g.qubits)
+        arr[i].q[0] = g.qubits[0]
+        arr[i].q[1] = g.qubits[1] if len(g.qubits) > 1 else -1
+        arr[i].layer = g.cycle
+        flat = np.asarray(g.matrix, np.complex128).reshape(-1)
+        for e, v in enumerate(flat):
+            arr[i].mat[2 * e] = v.real
+            arr[i].mat[2 * e + 1] = v.imag
+    c = _lib.lf_circuit(circuit.n_qubits, n, ctypes.cast(arr, ctypes.POINTER(_lib.lf_gate)))
+    return c, arr
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """Opaque plan handle (lf_plan); destroyed with close() or on collection."""
+
+    def __init__(self, circuit, open_qubits: Sequence[int], closed_bits: Sequence[int],
+                 dtype: str = "c64", max_log2: int = 28, n_sliced: int = -1,
+                 sliced_wires: Optional[Sequence[Tuple[int, int]]] = None,
+                 cost_model: str = "flopmem", greedy_trials: int = 8,
+                partition_trials: int = 64, sa_iters: int = 0,
+                 seed: int = 1, chalf_min_log2: int = 16, launch: str = "stream",
+                 check_overflow: bool = True, slices_per_graph: int = 8):
+        lib = _lib.load()
+        self._lib = lib
+        self._handle = ctypes.c_void_p()
+        self.n_qubits = circuit.n_qubits
+        self.open_qubits = [int(q) for q in open_qubits]
+        self.closed_bits = np.asarray(closed_bits, np.uint64)
+        opts = _lib.lf_plan_opts()
+        lib.lf_plan_opts_default(ctypes.byref(opts))
+        opts.dtype = DTYPES[dtype]
+        opts.max_log2_intermediate = max_log2
+        opts.n_sliced_wires = n_sliced
+        keep = None
+        if sliced_wires:
+            flat = np.asarray(sliced_wires, np.int32).reshape(-1)
+            keep = (ctypes.c_int32 * flat.size)(*flat.tolist())
+            opts.sliced_wires = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
+            opts.n_forced = len(sliced_wires)
+        opts.cost_model = COST[cost_model]
+        opts.greedy_trials = greedy_trials
+        opts.partition_trials = partition_trials
+        opts.sa_iters = sa_iters
+        opts.seed = seed
+        opts.chalf_min_log2 = chalf_min_log2
+        opts.launch_mode = LAUNCH[launch]
+        opts.check_overflow = 1 if check_overflow else 0
+        opts.slices_per_graph = slices_per_graph
+        c, arr = _circuit_struct(circuit)
+        openq = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
+        cb = np.ascontiguousarray(self.closed_bits)
+        st = lib.lf_build_network(ctypes.byref(c), openq, len(self.open_qubits),
+                                  cb.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), cb.size,
+                                  ctypes.byref(opts), ctypes.byref(self._handle))
+        del arr, keep
+        check(st, "lf_build_network")
+        self.workspace = None
+        self.dtype = dtype
+
+    # ---------------------------------------------------------------- info
+    def info(self) -> dict:
+        inf = _lib.lf_plan_info()
+        check(self._lib.lf_plan_get_info(self._handle, ctypes.byref(inf)), "lf_plan_get_info")
+        return {name: getattr(inf, name) for name, _ in inf._fields_}
+
+    def sliced_wires(self) -> List[Tuple[int, int]]:
+        n = self.info()["n_sliced_wires"]
+        buf = (ctypes.c_int32 * max(1, 2 * n))()
+        check(self._lib.lf_plan_sliced_wires(self._handle, buf), "lf_plan_sliced_wires")
+        return [(buf[2 * t], buf[2 * t + 1]) for t in range(n)]
+
+    def tree(self):
+        """(leaf canonical ids, [(left, right)] per step, id_base)."""
+        inf = self.info()
+        L, S = inf["n_leaves"], inf["n_steps"]
+        lc = (ctypes.c_int32 * max(1, L))()
+        le = (ctypes.c_int32 * max(1, S))()
+        ri = (ctypes.c_int32 * max(1, S))()
+        check(self._lib.lf_plan_tree(self._handle, lc, le, ri), "lf_plan_tree")
+        return [lc[i] for i in range(L)], [(le[s], ri[s]) for s in range(S)], inf["leaf_id_base"]
+
+    def steps(self):
+        """int32 [n_steps, 8] (nz, nm, nn, nk, variant, dtype, out_dtype, kernel), macs, bytes."""
+        S = self.info()["n_steps"]
+        dims = np.zeros((max(1, S), 8), np.int32)
+        macs = np.zeros(max(1, S))
+        byts = np.zeros(max(1, S))
+        check(self._lib.lf_plan_steps(self._handle,
+                                      dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      macs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      byts.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+              "lf_plan_steps")
+        return dims[:S], macs[:S], byts[:S]
+
+    # ------------------------------------------------------------- device
+    def bind(self, workspace=None, stream=None):
+        """Binds (allocating with torch if not given) the device workspace."""
+        import torch
+        need = int(self.info()["workspace_bytes"])
+        if workspace is None:
+            workspace = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        base = workspace.data_ptr()
+        pad = (-base) % 256
+        check(self._lib.lf_plan_bind_workspace(self._handle, ctypes.c_void_p(base + pad),
+                                               workspace.numel() - pad, _stream_ptr(stream)),
+              "lf_plan_bind_workspace")
+        self.workspace = workspace
+        return self
+
+    def new_amplitudes(self):
+        import torch
+        return torch.zeros((self.closed_bits.size, 1 << len(self.open_qubits)),
+                           dtype=torch.complex128, device="cuda")
+
+    def contract(self, begin: int, end: int, out=None, stream=None):
+        """Adds slices [begin, end) into out (complex128 [n_batch, 2^l]); returns out."""
+        if out is None:
+            out = self.new_amplitudes()
+        if out.dtype.__str__() != "torch.complex128" or not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex128 tensor")
+        if out.numel() != self.closed_bits.size << len(self.open_qubits):
+            raise ValueError("out has the wrong number of amplitudes")
+        check(self._lib.lf_contract_slices(self._handle, int(begin), int(end),
+                                           ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+              "lf_contract_slices")
+        return out
+
+    def profile_steps(self, reps: int = 3, stream=None) -> np.ndarray:
+        S = self.info()["n_steps"]
+        out = np.zeros(max(1, S))
+        check(self._lib.lf_profile_steps(self._handle, reps,
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         _stream_ptr(stream)), "lf_profile_steps")
+        return out[:S]
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            self._lib.lf_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_network(circuit, open_qubits, closed_bits, **opts) -> Plan:
+    return Plan(circuit, open_qubits, closed_bits, **opts)
+
+
+def contract_slices(plan: Plan, begin: int, end: int, out_amps=None, stream=None):
+    return plan.contract(begin, end, out_amps, stream)
+
+
+def postselect_topk(amps, group_size: int, k: int, stream=None):
+    """Top-k per group of `group_size` consecutive amplitudes (device tensors)."""
+    import torch
+    if amps.dtype != torch.complex128 or not amps.is_contiguous() or not amps.is_cuda:
+        raise ValueError("amps must be a contiguous complex128 CUDA tensor")
+    n = amps.numel()
+    if group_size <= 0 or n % group_size:
+        raise ValueError("amplitude count must be a multiple of group_size")
+    g = n // group_size
+    idx = torch.empty((g, k), dtype=torch.int64, device=amps.device)
+    prob = torch.empty((g, k), dtype=torch.float64, device=amps.device)
+    check(_lib.load().lf_postselect_topk(ctypes.c_void_p(amps.data_ptr()), g, group_size, k,
+                                         ctypes.c_void_p(idx.data_ptr()),
+                                         ctypes.c_void_p(prob.data_ptr()), _stream_ptr(stream)),
+          "lf_postselect_topk")
+    return idx, prob
+
+
+def contract_pair(A, B, C, nz: int, nm: int, nn: int, nk: int, c_strides, scale: float = 1.0,
+                  kernel: int = -1, stream=None):
+    """lf_contract_pair on device tensors.  A, B, C are torch tensors holding
+    (re, im) pairs: complex64 (float32 pairs) or complex-half (float16 pairs
+    with a trailing dimension of 2)."""
+    import torch
+
+    def dt(t):
+        if t.dtype == torch.complex64:
+            return _lib.LF_C64
+        if t.dtype == torch.float16:
+            return _lib.LF_CHALF
+        raise ValueError("tensors must be complex64 or float16 pairs")
+
+    if dt(A) != dt(B):
+        raise ValueError("A and B must share a dtype")
+    st = np.ascontiguousarray(np.asarray(c_strides, np.int64))
+    if st.size != nz + nm + nn:
+        raise ValueError("need nz + nm + nn strides")
+    check(_lib.load().lf_contract_pair(dt(A), dt(C), kernel, ctypes.c_void_p(A.data_ptr()),
+                                       ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()),
+                                       nz, nm, nn, nk,
+                                       st.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       float(scale), _stream_ptr(stream)), "lf_contract_pair")
+    return C

@@ -1,0 +1,71 @@
+// Device kernels of the contraction path (gfx950).  Launch wrappers only;
+// see kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lf {
+
+constexpr int MAXZ = 20;
+constexpr int MAXMN = 40;
+
+// One pairwise contraction C[z,m,n] = sum_k A[z,m,k] * B[z,n,k] over complex
+// numbers stored as (re, im) pairs.  A is read as a row-major
+// [2^nz][2^nm][2^nk] array, B as [2^nz][2^nn][2^nk]; C element (z,m,n) is at
+// sum of the strides of the set bits of z, m and n (cz, cm, cn; bit 0 the
+// least significant), so the result lands in any index order without a
+// permutation pass.  The accumulated value is multiplied by `scale`
+// (a power of two) before it is stored.
+//
+// In a batched product the [m][k] block of A for batch entry z starts at
+// element offA[z] (and B's [n][k] block at offB[z]); a null table means the
+// plain row-major position z * 2^(nm+nk) (z * 2^(nn+nk)).
+struct GettArgs {
+  const void* A;
+  const void* B;
+  void* C;
+  const int64_t* offA;
+  const int64_t* offB;
+  int nz, nm, nn, nk;
+  float scale;
+  int amax_only;      // 1: record the largest |re|,|im| only, store nothing
+  float* amax;        // nullable: running max of |re|,|im| of stored values (as bits)
+  unsigned* sat;      // nullable: count of values clamped to the half range
+  int64_t cz[MAXZ];
+  int64_t cm[MAXMN];
+  int64_t cn[MAXMN];
+};
+
+enum KernelId : int { K_THIN = 0, K_MFMA = 1, K_MFMA_SMALLK = 2, K_COUNT = 3 };
+
+// in_dt / out_dt: 0 complex64 (float pairs), 1 complex-half (_Float16 pairs)
+hipError_t launch_gett(int kernel, int in_dt, int out_dt, const GettArgs& a, hipStream_t s);
+bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk);
+
+// Copies of the slice-dependent blocks of leaf tensors.
+struct SliceCopy {
+  int64_t src;        // byte offset in the workspace of the full leaf
+  int64_t dst;        // byte offset of the per-slice copy
+  int64_t n;          // elements per slice block
+  int32_t es;         // element bytes (8 complex64, 4 complex-half)
+  int32_t nbits;      // sliced wires in this leaf
+  int32_t t[8];       // slice-number bit of each
+  int64_t stride[8];  // byte stride of each in the full leaf
+};
+hipError_t launch_instantiate(const SliceCopy* tab, int n_entries, int64_t max_n, char* ws,
+                              const int64_t* sigma_dev, int64_t sigma, hipStream_t s);
+
+// out[i] += root[i] * scale for i < n (complex128 accumulator, float64 math)
+hipError_t launch_accumulate(int root_dt, const void* root, double* out, int64_t n, double scale,
+                             hipStream_t s);
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
+hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t s);
+
+hipError_t launch_topk(const double* amps, int64_t n_groups, int64_t group_size, int k,
+                       int64_t* out_idx, double* out_prob, hipStream_t s);
+
+}  // namespace lf

@@ -1,0 +1,479 @@
+// Device kernels of the sliced contraction path, written for gfx950
+// (64-wide wavefronts, MFMA matrix cores, LDS).
+//
+// Complex products on MFMA (Methods C: each step is a pairwise contraction;
+// the paper ran it with a vendor einsum or transpose-GEMM, here it is one
+// kernel that reads operands in place).  A complex product
+// C = sum_k A[m,k] B[n,k] is the real product of A viewed as an m x 2K real
+// matrix ((re, im) interleaved, exactly as stored) with a 2N x 2K real
+// matrix B' whose rows 2n and 2n+1 are (Br, -Bi) and (Bi, Br) interleaved:
+//   row 2n   : sum Ar Br - Ai Bi = Re C
+//   row 2n+1 : sum Ar Bi + Ai Br = Im C
+// This is the four-real-product form; B' is built in LDS while the tile is
+// staged, and the accumulator rows 2n, 2n+1 land in the same lane, so each
+// lane writes whole complex numbers.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace lf {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+constexpr float HALF_MAX = 65504.0f;
+
+__device__ __forceinline__ int64_t scatter_bits(int64_t v, const int64_t* st, int nb) {
+  int64_t s = 0;
+  for (int b = 0; b < nb; ++b)
+    if ((v >> b) & 1) s += st[b];
+  return s;
+}
+
+// ------------------------------------------------------------ element io
+template <typename T> struct CIO;
+template <> struct CIO<float> {
+  __device__ static __forceinline__ void load(const float* p, int64_t i, float& re, float& im) {
+    float2 v = reinterpret_cast<const float2*>(p)[i];
+    re = v.x;
+    im = v.y;
+  }
+  __device__ static __forceinline__ unsigned store(float* p, int64_t i, float re, float im) {
+    reinterpret_cast<float2*>(p)[i] = make_float2(re, im);
+    return 0;
+  }
+};
+template <> struct CIO<_Float16> {
+  __device__ static __forceinline__ void load(const _Float16* p, int64_t i, float& re, float& im) {
+    f16x2 v = reinterpret_cast<const f16x2*>(p)[i];
+    re = float(v[0]);
+    im = float(v[1]);
+  }
+  __device__ static __forceinline__ unsigned store(_Float16* p, int64_t i, float re, float im) {
+    unsigned bad = 0;
+    if (!(fabsf(re) <= HALF_MAX)) { bad = 1; re = (re != re) ? 0.0f : copysignf(HALF_MAX, re); }
+    if (!(fabsf(im) <= HALF_MAX)) { bad = 1; im = (im != im) ? 0.0f : copysignf(HALF_MAX, im); }
+    f16x2 v;
+    v[0] = (_Float16)re;
+    v[1] = (_Float16)im;
+    reinterpret_cast<f16x2*>(p)[i] = v;
+    return bad;
+  }
+};
+
+__device__ __forceinline__ void block_amax_sat(float local_max, unsigned local_sat, float* amax,
+                                               unsigned* sat) {
+  // wave reduction, then one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) {
+    local_max = fmaxf(local_max, __shfl_xor(local_max, o));
+    local_sat += __shfl_xor(local_sat, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (amax && local_max > 0.0f) atomicMax(reinterpret_cast<unsigned*>(amax), __float_as_uint(local_max));
+    if (sat && local_sat) atomicAdd(sat, local_sat);
+  }
+}
+
+// --------------------------------------------------------------- thin
+// One thread per (z, m) row; up to 8 result columns per pass.  Used for
+// steps with a narrow side (a large tensor against a gate or small branch),
+// which are bound by HBM traffic: every A element is read once, every C
+// element written once.
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) gett_thin(GettArgs a) {
+  constexpr int NB = 8;
+  const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
+  const int64_t rows = (int64_t(1) << a.nz) * M;
+  __shared__ int64_t cnT[256];
+  for (int n = threadIdx.x; n < N && n < 256; n += blockDim.x) cnT[n] = scatter_bits(n, a.cn, a.nn);
+  __syncthreads();
+  const TI* A = static_cast<const TI*>(a.A);
+  const TI* B = static_cast<const TI*>(a.B);
+  TO* C = static_cast<TO*>(a.C);
+  float lmax = 0.0f;
+  unsigned lsat = 0;
+  for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < rows;
+       r += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t z = r >> a.nm, m = r & (M - 1);
+    const int64_t cbase = scatter_bits(z, a.cz, a.nz) + scatter_bits(m, a.cm, a.nm);
+    const int64_t arow = (a.offA ? a.offA[z] : z * M * K) + m * K;
+    const int64_t bz = a.offB ? a.offB[z] : z * N * K;
+    for (int64_t n0 = 0; n0 < N; n0 += NB) {
+      float cr[NB], ci[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) { cr[j] = 0.0f; ci[j] = 0.0f; }
+      for (int64_t k = 0; k < K; ++k) {
+        float ar, ai;
+        CIO<TI>::load(A, arow + k, ar, ai);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if (n0 + j < N) {
+            float br, bi;
+            CIO<TI>::load(B, bz + (n0 + j) * K + k, br, bi);
+            cr[j] += ar * br - ai * bi;
+            ci[j] += ar * bi + ai * br;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        int64_t n = n0 + j;
+        if (n >= N) break;
+        float re = cr[j] * a.scale, im = ci[j] * a.scale;
+        lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+        if (!a.amax_only) {
+          int64_t off = cbase + (n < 256 ? cnT[n] : scatter_bits(n, a.cn, a.nn));
+          lsat += CIO<TO>::store(C, off, re, im);
+        }
+      }
+    }
+  }
+  block_amax_sat(lmax, lsat, a.amax, a.sat);
+}
+
+// --------------------------------------------------------------- MFMA
+// Block tile: 128 values of m by 64 complex values of n (128 rows of B'),
+// four waves in a 2 x 2 arrangement, each owning 2 x 2 MFMA 32x32 blocks.
+// MFMA operand "A" is the expanded B' tile (rows n'), operand "B" is the A
+// tile (columns m), so a lane's accumulator rows 2n, 2n+1 are re, im of one
+// complex result.
+template <typename TI> struct MfmaTraits;
+template <> struct MfmaTraits<float> {
+  static constexpr int BK = 16;   // complex k per LDS tile
+  static constexpr int KS = 2;    // reals per MFMA
+  static constexpr int PAD = 4;
+};
+template <> struct MfmaTraits<_Float16> {
+  static constexpr int BK = 32;
+  static constexpr int KS = 16;
+  static constexpr int PAD = 8;
+};
+
+constexpr int MF_BM = 128;
+constexpr int MF_BN = 64;
+
+template <typename TI>
+__device__ __forceinline__ f32x16 mfma_step(const TI* sB, const TI* sA, int rowB, int rowA, int lda,
+                                            int kk, int lane, f32x16 acc);
+
+template <>
+__device__ __forceinline__ f32x16 mfma_step<float>(const float* sB, const float* sA, int rowB,
+                                                   int rowA, int lda, int kk, int lane, f32x16 acc) {
+  float x = sB[rowB * lda + kk + (lane >> 5)];
+  float y = sA[rowA * lda + kk + (lane >> 5)];
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ f32x16 mfma_step<_Float16>(const _Float16* sB, const _Float16* sA,
+                                                      int rowB, int rowA, int lda, int kk, int lane,
+                                                      f32x16 acc) {
+  f16x8 x = *reinterpret_cast<const f16x8*>(&sB[rowB * lda + kk + 8 * (lane >> 5)]);
+  f16x8 y = *reinterpret_cast<const f16x8*>(&sA[rowA * lda + kk + 8 * (lane >> 5)]);
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, acc, 0, 0, 0);
+}
+
+// 16-byte chunk of CPC complex values
+template <typename TI> struct Chunk {
+  static constexpr int CPC = 16 / (2 * int(sizeof(TI)));
+};
+
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
+  using Tr = MfmaTraits<TI>;
+  constexpr int BK = Tr::BK, BK2 = 2 * BK, LDA = BK2 + Tr::PAD;
+  constexpr int CPC = Chunk<TI>::CPC;          // complex per 16 B
+  constexpr int CH_ROW = BK / CPC;             // 16 B chunks per tile row
+  __shared__ __attribute__((aligned(16))) TI sA[MF_BM * LDA];
+  __shared__ __attribute__((aligned(16))) TI sB[2 * MF_BN * LDA];
+  __shared__ int64_t cmT[MF_BM];
+  __shared__ int64_t cnT[MF_BN];
+
+  const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
+  const int64_t mt = (M + MF_BM - 1) / MF_BM, nt = (N + MF_BN - 1) / MF_BN;
+  int64_t bid = blockIdx.x;
+  const int64_t tn = bid % nt;
+  bid /= nt;
+  const int64_t tm = bid % mt;
+  const int64_t z = bid / mt;
+  const int64_t m0 = tm * MF_BM, n0 = tn * MF_BN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wn = w & 1, wm = w >> 1;
+  const int validM = int(M - m0 < MF_BM ? M - m0 : MF_BM);
+  const int validN = int(N - n0 < MF_BN ? N - n0 : MF_BN);
+
+  for (int i = tid; i < MF_BM; i += 256) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
+  for (int i = tid; i < MF_BN; i += 256) cnT[i] = scatter_bits(n0 + i, a.cn, a.nn);
+  const int64_t czv = scatter_bits(z, a.cz, a.nz);
+
+  const TI* Ab = static_cast<const TI*>(a.A) + 2 * ((a.offA ? a.offA[z] : z * M * K) + m0 * K);
+  const TI* Bb = static_cast<const TI*>(a.B) + 2 * ((a.offB ? a.offB[z] : z * N * K) + n0 * K);
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+    // A tile: MF_BM rows x CH_ROW chunks
+    for (int c = tid; c < MF_BM * CH_ROW; c += 256) {
+      const int r = c / CH_ROW, ch = c % CH_ROW;
+      const int64_t kc = k0 + int64_t(ch) * CPC;
+      TI* dst = &sA[r * LDA + 2 * ch * CPC];
+      if (r < validM && kc + CPC <= K) {
+        *reinterpret_cast<float4*>(dst) =
+            *reinterpret_cast<const float4*>(Ab + 2 * (int64_t(r) * K + kc));
+      } else {
+#pragma unroll
+        for (int e = 0; e < CPC; ++e) {
+          const bool ok = r < validM && kc + e < K;
+          dst[2 * e] = ok ? Ab[2 * (int64_t(r) * K + kc + e)] : TI(0);
+          dst[2 * e + 1] = ok ? Ab[2 * (int64_t(r) * K + kc + e) + 1] : TI(0);
+        }
+      }
+    }
+    // B tile, expanded to B' rows 2n, 2n+1
+    for (int c = tid; c < MF_BN * CH_ROW; c += 256) {
+      const int r = c / CH_ROW, ch = c % CH_ROW;
+      const int64_t kc = k0 + int64_t(ch) * CPC;
+      TI re[CPC], im[CPC];
+      if (r < validN && kc + CPC <= K) {
+        TI tmp[2 * CPC];
+        *reinterpret_cast<float4*>(tmp) = *reinterpret_cast<const float4*>(Bb + 2 * (int64_t(r) * K + kc));
+#pragma unroll
+        for (int e = 0; e < CPC; ++e) { re[e] = tmp[2 * e]; im[e] = tmp[2 * e + 1]; }
+      } else {
+#pragma unroll
+        for (int e = 0; e < CPC; ++e) {
+          const bool ok = r < validN && kc + e < K;
+          re[e] = ok ? Bb[2 * (int64_t(r) * K + kc + e)] : TI(0);
+          im[e] = ok ? Bb[2 * (int64_t(r) * K + kc + e) + 1] : TI(0);
+        }
+      }
+      TI row0[2 * CPC], row1[2 * CPC];
+#pragma unroll
+      for (int e = 0; e < CPC; ++e) {
+        row0[2 * e] = re[e];
+        row0[2 * e + 1] = -im[e];
+        row1[2 * e] = im[e];
+        row1[2 * e + 1] = re[e];
+      }
+      *reinterpret_cast<float4*>(&sB[(2 * r) * LDA + 2 * ch * CPC]) = *reinterpret_cast<float4*>(row0);
+      *reinterpret_cast<float4*>(&sB[(2 * r + 1) * LDA + 2 * ch * CPC]) = *reinterpret_cast<float4*>(row1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK2; kk += Tr::KS) {
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm)
+          acc[bn][bm] = mfma_step<TI>(sB, sA, wn * 64 + bn * 32 + (lane & 31),
+                                      wm * 64 + bm * 32 + (lane & 31), LDA, kk, lane, acc[bn][bm]);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: lane holds column m, rows n' = 8(v/4) + 4(lane/32) + v%4
+  TO* C = static_cast<TO*>(a.C);
+  float lmax = 0.0f;
+  unsigned lsat = 0;
+#pragma unroll
+  for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm) {
+      const int ml = wm * 64 + bm * 32 + (lane & 31);
+      if (ml >= validM) continue;
+      const int64_t cb = czv + cmT[ml];
+#pragma unroll
+      for (int v = 0; v < 16; v += 2) {
+        const int np = wn * 64 + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int nl = np >> 1;
+        if (nl >= validN) continue;
+        const float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
+        lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+        if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
+      }
+    }
+  block_amax_sat(lmax, lsat, a.amax, a.sat);
+}
+
+// ------------------------------------------------------------ launchers
+bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
+  (void)in_dt;
+  (void)nz;
+  (void)nk;
+  if (kernel == K_THIN) return true;
+  if (kernel == K_MFMA) return nm >= 5 && nn >= 4;
+  return false;
+}
+
+template <typename TI, typename TO>
+static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
+  if (kernel == K_THIN) {
+    const int64_t rows = (int64_t(1) << a.nz) << a.nm;
+    int64_t blocks = (rows + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((gett_thin<TI, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+  } else {
+    const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn;
+    const int64_t blocks = (int64_t(1) << a.nz) * ((M + MF_BM - 1) / MF_BM) * ((N + MF_BN - 1) / MF_BN);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gett_mfma<TI, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gett(int kernel, int in_dt, int out_dt, const GettArgs& a, hipStream_t s) {
+  if (!kernel_applicable(kernel, in_dt, a.nz, a.nm, a.nn, a.nk)) kernel = K_THIN;
+  if (in_dt == 0 && out_dt == 0) return launch_typed<float, float>(kernel, a, s);
+  if (in_dt == 0 && out_dt == 1) return launch_typed<float, _Float16>(kernel, a, s);
+  if (in_dt == 1 && out_dt == 0) return launch_typed<_Float16, float>(kernel, a, s);
+  return launch_typed<_Float16, _Float16>(kernel, a, s);
+}
+
+// -------------------------------------------------------- slice copies
+__global__ void __launch_bounds__(256) instantiate_kernel(const SliceCopy* tab, char* ws,
+                                                          const int64_t* sigma_dev, int64_t sigma) {
+  const SliceCopy e = tab[blockIdx.y];
+  const int64_t sg = sigma_dev ? *sigma_dev : sigma;
+  int64_t off = 0;
+  for (int i = 0; i < e.nbits; ++i)
+    if ((sg >> e.t[i]) & 1) off += e.stride[i];
+  const char* src = ws + e.src + off;
+  char* dst = ws + e.dst;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < e.n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    if (e.es == 8) reinterpret_cast<uint64_t*>(dst)[i] = reinterpret_cast<const uint64_t*>(src)[i];
+    else reinterpret_cast<uint32_t*>(dst)[i] = reinterpret_cast<const uint32_t*>(src)[i];
+  }
+}
+
+hipError_t launch_instantiate(const SliceCopy* tab, int n_entries, int64_t max_n, char* ws,
+                              const int64_t* sigma_dev, int64_t sigma, hipStream_t s) {
+  if (n_entries == 0) return hipSuccess;
+  int64_t bx = (max_n + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(instantiate_kernel, dim3(unsigned(bx), unsigned(n_entries)), dim3(256), 0, s,
+                     tab, ws, sigma_dev, sigma);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- accumulate
+template <typename T>
+__global__ void __launch_bounds__(256) accumulate_kernel(const T* root, double* out, int64_t n,
+                                                         double scale) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    float re, im;
+    CIO<T>::load(root, i, re, im);
+    out[2 * i] += double(re) * scale;
+    out[2 * i + 1] += double(im) * scale;
+  }
+}
+
+hipError_t launch_accumulate(int root_dt, const void* root, double* out, int64_t n, double scale,
+                             hipStream_t s) {
+  int64_t b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  if (root_dt == 0)
+    hipLaunchKernelGGL(accumulate_kernel<float>, dim3(unsigned(b)), dim3(256), 0, s,
+                       static_cast<const float*>(root), out, n, scale);
+  else
+    hipLaunchKernelGGL(accumulate_kernel<_Float16>, dim3(unsigned(b)), dim3(256), 0, s,
+                       static_cast<const _Float16*>(root), out, n, scale);
+  return hipGetLastError();
+}
+
+__global__ void set_i64_kernel(int64_t* p, int64_t v) { *p = v; }
+__global__ void add_i64_kernel(int64_t* p, int64_t v) { *p += v; }
+__global__ void zero_u32_kernel(unsigned* p, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(add_i64_kernel, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t s) {
+  int64_t b = (n + 255) / 256;
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(unsigned(b)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- top-k
+// One workgroup per group.  Round r finds the best entry strictly after the
+// (r-1)-th selection in the order (p descending, position ascending):
+// per-lane scan, wave shuffle reduction, then across the four waves.
+__device__ __forceinline__ bool topk_better(double p, int64_t j, double q, int64_t i) {
+  return p > q || (p == q && j < i);
+}
+
+__global__ void __launch_bounds__(256) topk_kernel(const double* amps, int64_t group_size, int k,
+                                                   int64_t* out_idx, double* out_prob) {
+  __shared__ double sp[4];
+  __shared__ int64_t sj[4];
+  const int64_t g = blockIdx.x;
+  const double* base = amps + 2 * g * group_size;
+  double prev_p = 0.0;
+  int64_t prev_j = -1;
+  bool have_prev = false;
+  for (int r = 0; r < k; ++r) {
+    double bp = -1.0;
+    int64_t bj = INT64_MAX;
+    for (int64_t j = threadIdx.x; j < group_size; j += blockDim.x) {
+      const double re = base[2 * j], im = base[2 * j + 1];
+      const double p = __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+      const bool after = !have_prev || p < prev_p || (p == prev_p && j > prev_j);
+      if (after && topk_better(p, j, bp, bj)) { bp = p; bj = j; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double op = __shfl_xor(bp, o);
+      const int64_t oj = __shfl_xor(bj, o);
+      if (topk_better(op, oj, bp, bj)) { bp = op; bj = oj; }
+    }
+    if ((threadIdx.x & 63) == 0) { sp[threadIdx.x >> 6] = bp; sj[threadIdx.x >> 6] = bj; }
+    __syncthreads();
+    double fp = sp[0];
+    int64_t fj = sj[0];
+    for (int i = 1; i < int(blockDim.x >> 6); ++i)
+      if (topk_better(sp[i], sj[i], fp, fj)) { fp = sp[i]; fj = sj[i]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      out_idx[g * k + r] = fj;
+      out_prob[g * k + r] = fp;
+    }
+    prev_p = fp;
+    prev_j = fj;
+    have_prev = true;
+  }
+}
+
+hipError_t launch_topk(const double* amps, int64_t n_groups, int64_t group_size, int k,
+                       int64_t* out_idx, double* out_prob, hipStream_t s) {
+  if (n_groups <= 0) return hipSuccess;
+  if (n_groups > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(topk_kernel, dim3(unsigned(n_groups)), dim3(256), 0, s, amps, group_size, k,
+                     out_idx, out_prob);
+  return hipGetLastError();
+}
+
+}  // namespace lf

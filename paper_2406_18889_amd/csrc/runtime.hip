@@ -1,0 +1,772 @@
+// Plan runtime and the extern "C" boundary (include/leapfrog.h).
+//
+// Workspace layout (one caller-owned device buffer, 256-byte aligned
+// pieces):
+//   [leaves]        every leaf tensor in full, in its storage type and layout
+//   [slice leaves]  per-slice copies of the leaves that carry sliced wires
+//   [invariant]     results of slice-independent subtrees (kept across slices)
+//   [variant]       slice-dependent intermediates, packed by lifetime
+//   [control]       slice counter, saturation counter, per-step amax
+//   [tables]        slice-copy descriptors
+//
+// Complex-half scaling: every complex-half tensor T carries an integer
+// exponent e_T with value = stored * 2^e_T.  Leaves get e from their largest
+// entry.  For a step producing a complex-half tensor, the stored result is
+// acc * 2^s where acc is the float32 accumulation of stored operands, and
+// e_C = e_A + e_B - s.  The shift s of each step is calibrated once per plan
+// on the first contracted slice by a pass that only records the largest
+// |re|,|im| of acc, targeting 2^12 (four bits of headroom below the half
+// maximum 65504); later slices reuse it and count every value clamped to the
+// half range.  Results stored as complex64 fold 2^(e_A + e_B) into their
+// scale and carry e = 0.  The final sum into float64 multiplies by 2^e_root.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/leapfrog.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace lf {
+const CostFn* mlp_cost_fn();  // costmodel.cpp (nullptr when no model is loaded)
+}
+
+namespace {
+thread_local std::string g_err;
+lf_status fail(lf_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess) return fail(LF_HIP_ERROR, std::string(#x ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int64_t ALIGN = 256;
+int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+}  // namespace
+
+struct lf_plan {
+  lf_plan_opts opts{};
+  lf::Network net;
+  lf::HostPlan hp;
+  int n_nodes = 0;
+  int root = -1;
+  // per node
+  std::vector<int> store_dt;       // storage type
+  std::vector<int64_t> elems;      // per-slice elements
+  std::vector<int64_t> off;        // byte offset of the tensor a step reads
+  std::vector<int64_t> full_off;   // leaves: byte offset of the full tensor
+  std::vector<int> exp2;           // power-of-two exponent (complex-half)
+  std::vector<int> shift;          // per step (complex-half results)
+  std::vector<lf::SliceCopy> copies;
+  std::vector<int64_t> gtab_off;   // per step: byte offset of [offA | offB] tables, -1 if none
+  int64_t copy_max_n = 0;
+  int64_t off_copies_tab = 0, off_sigma = 0, off_sat = 0, off_amax = 0;
+  uint64_t ws_bytes = 0;
+  std::vector<int> variant_steps, invariant_steps;
+  // binding
+  char* ws = nullptr;
+  uint64_t ws_size = 0;
+  bool bound = false;
+  bool invariant_done = false;
+  bool calibrated = false;
+  // graph cache
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  void* graph_out = nullptr;
+  hipStream_t graph_stream = nullptr;
+  int graph_slices = 0;
+  hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
+  ~lf_plan() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+namespace {
+
+using namespace lf;
+
+int leaf_count(const lf_plan* p) { return p->hp.tree.n_leaves; }
+
+// -------------------------------------------------------- memory planning
+std::string plan_memory(lf_plan* P) {
+  const HostPlan& hp = P->hp;
+  const Network& net = P->net;
+  const int L = hp.tree.n_leaves;
+  const int N = L + int(hp.tree.left.size());
+  P->n_nodes = N;
+  P->root = N - 1;
+  for (int i = 0; i < N; ++i) if (hp.tree.parent[i] < 0) P->root = i;
+  std::vector<int> bits_of(net.indices.size());
+  for (size_t i = 0; i < net.indices.size(); ++i) bits_of[i] = net.indices[i].bits;
+  std::vector<char> is_sliced(net.indices.size(), 0);
+  for (int x : hp.sliced) is_sliced[x] = 1;
+
+  P->store_dt.assign(N, 0);
+  P->elems.assign(N, 1);
+  P->off.assign(N, -1);
+  P->full_off.assign(N, -1);
+  P->exp2.assign(N, 0);
+  P->shift.assign(hp.steps.size(), 0);
+  for (int n = 0; n < N; ++n) {
+    int w = 0;
+    for (int x : hp.order[n]) if (!is_sliced[x]) w += bits_of[x];
+    P->elems[n] = int64_t(1) << w;
+    int par = hp.tree.parent[n];
+    if (par >= 0) P->store_dt[n] = hp.steps[hp.step_of_node[par]].dtype;
+    else if (n >= L) P->store_dt[n] = hp.steps[hp.step_of_node[n]].out_dtype;
+    else P->store_dt[n] = 0;
+  }
+  auto bytes_of = [&](int n) { return P->elems[n] * (P->store_dt[n] ? 4 : 8); };
+
+  int64_t cur = 0;
+  // leaves in full
+  std::vector<int> n_sl(L, 0);
+  for (int i = 0; i < L; ++i) {
+    for (int x : hp.order[i]) if (is_sliced[x]) n_sl[i]++;
+    int64_t b = bytes_of(i) << n_sl[i];
+    P->full_off[i] = cur;
+    cur += align_up(b);
+  }
+  // per-slice copies
+  P->copies.clear();
+  P->copy_max_n = 0;
+  for (int i = 0; i < L; ++i) {
+    if (!n_sl[i]) { P->off[i] = P->full_off[i]; continue; }
+    P->off[i] = cur;
+    SliceCopy c{};
+    c.src = P->full_off[i];
+    c.dst = cur;
+    c.n = P->elems[i];
+    c.es = P->store_dt[i] ? 4 : 8;
+    c.nbits = n_sl[i];
+    if (c.nbits > 8) return "a leaf carries more than 8 sliced wires";
+    // sliced wires are the leading indices of the leaf layout
+    int64_t stride = int64_t(c.es) * P->elems[i];
+    for (int q = n_sl[i] - 1; q >= 0; --q) {
+      int x = hp.order[i][q];
+      int t = int(std::find(hp.sliced.begin(), hp.sliced.end(), x) - hp.sliced.begin());
+      c.t[n_sl[i] - 1 - q] = t;
+      c.stride[n_sl[i] - 1 - q] = stride;
+      stride *= 2;
+    }
+    P->copies.push_back(c);
+    P->copy_max_n = std::max(P->copy_max_n, c.n);
+    cur += align_up(bytes_of(i));
+  }
+  // step classes
+  P->variant_steps.clear();
+  P->invariant_steps.clear();
+  for (size_t s = 0; s < hp.steps.size(); ++s)
+    (hp.steps[s].variant ? P->variant_steps : P->invariant_steps).push_back(int(s));
+  // invariant results: permanent
+  for (int s : P->invariant_steps) {
+    int n = hp.steps[s].out;
+    P->off[n] = cur;
+    cur += align_up(bytes_of(n));
+  }
+  // variant results: interval packing over the per-slice step sequence
+  struct Item { int node; int64_t bytes; int start, end; int64_t off; };
+  std::vector<Item> items;
+  std::vector<int> pos_of_step(hp.steps.size(), -1);
+  for (size_t i = 0; i < P->variant_steps.size(); ++i) pos_of_step[P->variant_steps[i]] = int(i);
+  const int nv = int(P->variant_steps.size());
+  for (int s : P->variant_steps) {
+    int n = hp.steps[s].out;
+    int par = hp.tree.parent[n];
+    int end = par < 0 ? nv : pos_of_step[hp.step_of_node[par]];
+    items.push_back({n, align_up(bytes_of(n)), pos_of_step[s], end, -1});
+  }
+  std::vector<int> ordr(items.size());
+  for (size_t i = 0; i < ordr.size(); ++i) ordr[i] = int(i);
+  std::sort(ordr.begin(), ordr.end(), [&](int a, int b) { return items[a].bytes > items[b].bytes; });
+  std::vector<int> placed;
+  int64_t vpeak = 0;
+  for (int i : ordr) {
+    Item& it = items[i];
+    std::vector<std::pair<int64_t, int64_t>> busy;
+    for (int j : placed) {
+      const Item& o = items[j];
+      if (o.start <= it.end && it.start <= o.end) busy.push_back({o.off, o.off + o.bytes});
+    }
+    std::sort(busy.begin(), busy.end());
+    int64_t at = 0;
+    for (auto& b : busy) {
+      if (at + it.bytes <= b.first) break;
+      at = std::max(at, b.second);
+    }
+    it.off = at;
+    placed.push_back(i);
+    vpeak = std::max(vpeak, at + it.bytes);
+  }
+  for (auto& it : items) P->off[it.node] = cur + it.off;
+  cur += align_up(vpeak);
+  // gather tables of batched steps: 2^nb offsets for A, then for B
+  P->gtab_off.assign(hp.steps.size(), -1);
+  for (size_t s = 0; s < hp.steps.size(); ++s) {
+    if (!hp.steps[s].batched) continue;
+    P->gtab_off[s] = cur;
+    cur += align_up(int64_t(2 * sizeof(int64_t)) << hp.steps[s].nz);
+  }
+  // control block
+  P->off_sigma = cur;
+  cur += ALIGN;
+  P->off_sat = cur;
+  cur += ALIGN;
+  P->off_amax = cur;
+  cur += align_up(int64_t(sizeof(float)) * std::max<size_t>(1, hp.steps.size()));
+  P->off_copies_tab = cur;
+  cur += align_up(int64_t(sizeof(SliceCopy)) * std::max<size_t>(1, P->copies.size()));
+  P->ws_bytes = uint64_t(cur);
+  return "";
+}
+
+// Leaf data in the stored layout (full, sliced wires leading), float64.
+void leaf_layout(const lf_plan* P, int i, std::vector<cd>& out) {
+  const Leaf& L = P->net.leaves[i];
+  const std::vector<int>& ord = P->hp.order[i];
+  const auto& ix = P->net.indices;
+  // source strides (row-major over L.idx)
+  std::vector<int64_t> sst(L.idx.size());
+  int64_t acc = 1;
+  for (int a = int(L.idx.size()) - 1; a >= 0; --a) { sst[a] = acc; acc <<= ix[L.idx[a]].bits; }
+  int64_t n = acc;
+  out.assign(n, cd(0));
+  std::vector<int64_t> src_stride_of_dst(ord.size());
+  std::vector<int> dbits(ord.size());
+  for (size_t d = 0; d < ord.size(); ++d) {
+    int a = int(std::find(L.idx.begin(), L.idx.end(), ord[d]) - L.idx.begin());
+    src_stride_of_dst[d] = sst[a];
+    dbits[d] = ix[ord[d]].bits;
+  }
+  for (int64_t e = 0; e < n; ++e) {
+    int64_t rem = e, src = 0;
+    for (int d = int(ord.size()) - 1; d >= 0; --d) {
+      int64_t dim = int64_t(1) << dbits[d];
+      src += (rem % dim) * src_stride_of_dst[d];
+      rem /= dim;
+    }
+    out[e] = L.data[src];
+  }
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+GettArgs step_args(const lf_plan* P, int s) {
+  const StepLayout& st = P->hp.steps[s];
+  GettArgs a{};
+  a.A = P->ws + P->off[st.a];
+  a.B = P->ws + P->off[st.b];
+  a.C = P->ws + P->off[st.out];
+  a.nz = st.nz;
+  a.nm = st.nm;
+  a.nn = st.nn;
+  a.nk = st.nk;
+  if (P->gtab_off[s] >= 0) {
+    a.offA = reinterpret_cast<const int64_t*>(P->ws + P->gtab_off[s]);
+    a.offB = a.offA + (int64_t(1) << st.nz);
+  }
+  for (int i = 0; i < st.nz; ++i) a.cz[i] = st.cz[i];
+  for (int i = 0; i < st.nm; ++i) a.cm[i] = st.cm[i];
+  for (int i = 0; i < st.nn; ++i) a.cn[i] = st.cn[i];
+  const int ea = P->exp2[st.a], eb = P->exp2[st.b];
+  if (P->store_dt[st.out] == 1) a.scale = std::ldexp(1.0f, P->shift[s]);
+  else a.scale = std::ldexp(1.0f, ea + eb);
+  a.amax_only = 0;
+  a.amax = reinterpret_cast<float*>(P->ws + P->off_amax) + s;
+  a.sat = reinterpret_cast<unsigned*>(P->ws + P->off_sat);
+  return a;
+}
+
+lf_status run_step(lf_plan* P, int s, hipStream_t stream) {
+  const StepLayout& st = P->hp.steps[s];
+  GettArgs a = step_args(P, s);
+  hipError_t e = launch_gett(st.kernel, st.dtype, P->store_dt[st.out], a, stream);
+  if (e != hipSuccess) return fail(LF_HIP_ERROR, std::string("contraction launch: ") + hipGetErrorString(e));
+  return LF_OK;
+}
+
+// propagate exponents in step order (complex64 results carry 0)
+void propagate_exponents(lf_plan* P) {
+  for (size_t s = 0; s < P->hp.steps.size(); ++s) {
+    const StepLayout& st = P->hp.steps[s];
+    if (P->store_dt[st.out] == 1) P->exp2[st.out] = P->exp2[st.a] + P->exp2[st.b] - P->shift[s];
+    else P->exp2[st.out] = 0;
+  }
+}
+
+// Calibrate the complex-half shifts on slice `sigma`: for each step in order
+// whose result is stored in half, one pass records max |acc| without
+// storing, then the shift is set and the step runs for real.
+lf_status calibrate(lf_plan* P, int64_t sigma, hipStream_t stream) {
+  HIPCHK(launch_instantiate(reinterpret_cast<const SliceCopy*>(P->ws + P->off_copies_tab),
+                            int(P->copies.size()), P->copy_max_n, P->ws, nullptr, sigma, stream));
+  float* amax_dev = reinterpret_cast<float*>(P->ws + P->off_amax);
+  for (size_t s = 0; s < P->hp.steps.size(); ++s) {
+    const StepLayout& st = P->hp.steps[s];
+    if (P->store_dt[st.out] == 1) {
+      GettArgs a = step_args(P, int(s));
+      a.scale = 1.0f;
+      a.amax_only = 1;
+      HIPCHK(launch_zero_u32(reinterpret_cast<unsigned*>(amax_dev + s), 1, stream));
+      HIPCHK(launch_gett(st.kernel, st.dtype, 1, a, stream));
+      float mx = 0;
+      HIPCHK(hipMemcpyAsync(&mx, amax_dev + s, sizeof(float), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      int sh = 0;
+      if (mx > 0 && std::isfinite(mx)) sh = 12 - int(std::ceil(std::log2(double(mx))));
+      P->shift[s] = sh;
+      P->exp2[st.out] = P->exp2[st.a] + P->exp2[st.b] - sh;
+    } else {
+      P->exp2[st.out] = 0;
+    }
+    lf_status r = run_step(P, int(s), stream);
+    if (r) return r;
+  }
+  P->calibrated = true;
+  // a calibration pass leaves invariant results computed
+  P->invariant_done = true;
+  return LF_OK;
+}
+
+lf_status run_slice(lf_plan* P, const int64_t* sigma_dev, int64_t sigma, double* out,
+                    hipStream_t stream) {
+  HIPCHK(launch_instantiate(reinterpret_cast<const SliceCopy*>(P->ws + P->off_copies_tab),
+                            int(P->copies.size()), P->copy_max_n, P->ws, sigma_dev, sigma, stream));
+  for (int s : P->variant_steps) {
+    lf_status r = run_step(P, s, stream);
+    if (r) return r;
+  }
+  const int r = P->root;
+  const int64_t n = P->net.n_batch << P->net.open_qubits.size();
+  HIPCHK(launch_accumulate(P->store_dt[r], P->ws + P->off[r], out, n,
+                           std::ldexp(1.0, P->exp2[r]), stream));
+  return LF_OK;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+void lf_plan_opts_default(lf_plan_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->dtype = LF_C64;
+  o->max_log2_intermediate = 28;
+  o->n_sliced_wires = -1;
+  o->sliced_wires = nullptr;
+  o->n_forced = 0;
+  o->cost_model = LF_COST_FLOPMEM;
+  o->greedy_trials = 8;
+  o->partition_trials = 64;
+  o->sa_iters = 0;
+  o->seed = 1;
+  o->chalf_min_log2 = 16;
+  o->launch_mode = LF_LAUNCH_STREAM;
+  o->check_overflow = 1;
+  o->slices_per_graph = 8;
+}
+
+const char* lf_last_error(void) { return g_err.c_str(); }
+
+lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits, int32_t n_open,
+                           const uint64_t* closed_bits, int64_t n_batch, const lf_plan_opts* opts,
+                           lf_plan** out_plan) {
+  try {
+    if (!out_plan) return fail(LF_INVALID_ARGUMENT, "out_plan is NULL");
+    *out_plan = nullptr;
+    if (!circuit || (circuit->n_gates > 0 && !circuit->gates))
+      return fail(LF_INVALID_ARGUMENT, "circuit is NULL");
+    if (n_open < 0 || n_open > 30 || (n_open > 0 && !open_qubits))
+      return fail(LF_INVALID_ARGUMENT, "n_open must be in [0, 30]");
+    if (n_batch < 1 || !closed_bits) return fail(LF_INVALID_ARGUMENT, "need n_batch >= 1 closed strings");
+    lf_plan_opts o;
+    lf_plan_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.dtype != LF_C64 && o.dtype != LF_CHALF) return fail(LF_INVALID_ARGUMENT, "dtype");
+    if (o.max_log2_intermediate < 1 || o.max_log2_intermediate > 34)
+      return fail(LF_INVALID_ARGUMENT, "max_log2_intermediate must be in [1, 34]");
+    if (o.launch_mode != LF_LAUNCH_STREAM && o.launch_mode != LF_LAUNCH_GRAPH)
+      return fail(LF_INVALID_ARGUMENT, "launch_mode");
+    if (o.slices_per_graph < 1 || o.slices_per_graph > 1024)
+      return fail(LF_INVALID_ARGUMENT, "slices_per_graph must be in [1, 1024]");
+    std::vector<lf::GateIn> gates(circuit->n_gates);
+    for (int g = 0; g < circuit->n_gates; ++g) {
+      const lf_gate& G = circuit->gates[g];
+      lf::GateIn& d = gates[g];
+      d.nq = G.n_q;
+      d.q[0] = G.q[0];
+      d.q[1] = G.q[1];
+      int dim = G.n_q == 1 ? 2 : 4;
+      if (G.n_q != 1 && G.n_q != 2) return fail(LF_INVALID_ARGUMENT, "gate must act on 1 or 2 qubits");
+      for (int e = 0; e < dim * dim; ++e) d.m[e] = lf::cd(G.mat[2 * e], G.mat[2 * e + 1]);
+    }
+    std::vector<int> openq(open_qubits, open_qubits + n_open);
+    std::vector<uint64_t> cb(closed_bits, closed_bits + n_batch);
+    auto P = std::make_unique<lf_plan>();
+    P->opts = o;
+    std::string err = lf::build_network(circuit->n_qubits, gates, openq, cb, P->net);
+    if (!err.empty()) return fail(LF_INVALID_ARGUMENT, err);
+    lf::PlanOptions po;
+    po.max_log2 = o.max_log2_intermediate;
+    po.n_sliced = o.n_sliced_wires;
+    po.greedy_trials = std::max(0, o.greedy_trials);
+    po.partition_trials = std::max(0, o.partition_trials);
+    if (po.greedy_trials + po.partition_trials < 1) po.greedy_trials = 1;
+    po.sa_iters = long(std::max<int64_t>(0, o.sa_iters));
+    po.seed = o.seed;
+    po.cost_model = o.cost_model;
+    po.dtype = o.dtype;
+    po.chalf_min_log2 = o.chalf_min_log2;
+    if (o.n_forced > 0) {
+      if (!o.sliced_wires) return fail(LF_INVALID_ARGUMENT, "sliced_wires is NULL");
+      for (int t = 0; t < o.n_forced; ++t) {
+        int id = P->net.wire_id(o.sliced_wires[2 * t], o.sliced_wires[2 * t + 1]);
+        if (id < 0) return fail(LF_INVALID_ARGUMENT, "forced sliced wire is not an internal wire");
+        po.forced_slices.push_back(id);
+      }
+    }
+    const lf::CostFn* cf = nullptr;
+    if (o.cost_model == LF_COST_MLP) {
+      cf = lf::mlp_cost_fn();
+      if (!cf) return fail(LF_INVALID_ARGUMENT, "cost_model MLP requested but no model is loaded");
+    }
+    err = lf::plan_network(P->net, po, P->hp, cf);
+    if (!err.empty()) {
+      if (err.find("cap") != std::string::npos) return fail(LF_PLAN_INFEASIBLE, err);
+      return fail(LF_INTERNAL, err);
+    }
+    if (int(P->hp.sliced.size()) > 62) return fail(LF_PLAN_INFEASIBLE, "too many sliced wires");
+    // default kernel choice
+    for (auto& s : P->hp.steps)
+      s.kernel = lf::kernel_applicable(lf::K_MFMA, s.dtype, s.nz, s.nm, s.nn, s.nk) && s.nk >= 2
+                     ? lf::K_MFMA : lf::K_THIN;
+    for (auto& s : P->hp.steps)
+      if (s.nz > lf::MAXZ || s.nm > lf::MAXMN || s.nn > lf::MAXMN)
+        return fail(LF_PLAN_INFEASIBLE, "step rank exceeds kernel limits");
+    err = plan_memory(P.get());
+    if (!err.empty()) return fail(LF_PLAN_INFEASIBLE, err);
+    *out_plan = P.release();
+    return LF_OK;
+  } catch (const std::exception& e) {
+    return fail(LF_INTERNAL, e.what());
+  }
+}
+
+lf_status lf_plan_get_info(const lf_plan* P, lf_plan_info* out) {
+  if (!P || !out) return fail(LF_INVALID_ARGUMENT, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  out->n_sliced_wires = int32_t(P->hp.sliced.size());
+  out->n_slices = int64_t(1) << P->hp.sliced.size();
+  out->n_steps = int32_t(P->hp.steps.size());
+  out->n_variant_steps = int32_t(P->variant_steps.size());
+  out->n_leaves = P->hp.tree.n_leaves;
+  out->max_log2_intermediate = P->hp.max_log2;
+  out->dtype = P->opts.dtype;
+  out->n_open = int32_t(P->net.open_qubits.size());
+  out->n_batch = P->net.n_batch;
+  out->n_batch_log2 = P->net.nb;
+  int nh = 0;
+  for (auto& s : P->hp.steps) nh += s.dtype;
+  out->n_half_steps = nh;
+  out->macs_per_slice = P->hp.macs_variant;
+  out->macs_invariant = P->hp.macs_invariant;
+  out->bytes_per_slice = P->hp.bytes_variant;
+  out->bytes_invariant = P->hp.bytes_invariant;
+  out->log2_total_macs = P->hp.log2_total_cost;
+  out->workspace_bytes = P->ws_bytes;
+  out->leaf_id_base = P->net.n2q + P->net.n_qubits;
+  return LF_OK;
+}
+
+lf_status lf_plan_sliced_wires(const lf_plan* P, int32_t* qj) {
+  if (!P || (!qj && !P->hp.sliced.empty())) return fail(LF_INVALID_ARGUMENT, "NULL argument");
+  for (size_t t = 0; t < P->hp.sliced.size(); ++t) {
+    const lf::Index& ix = P->net.indices[P->hp.sliced[t]];
+    qj[2 * t] = ix.q;
+    qj[2 * t + 1] = ix.j;
+  }
+  return LF_OK;
+}
+
+lf_status lf_plan_tree(const lf_plan* P, int32_t* leaf_canon, int32_t* left, int32_t* right) {
+  if (!P || !leaf_canon || ((!left || !right) && !P->hp.steps.empty()))
+    return fail(LF_INVALID_ARGUMENT, "NULL argument");
+  const int L = P->hp.tree.n_leaves;
+  const int base = P->net.n2q + P->net.n_qubits;
+  for (int i = 0; i < L; ++i) leaf_canon[i] = P->net.leaves[i].canon_id;
+  auto id = [&](int node) {
+    return node < L ? P->net.leaves[node].canon_id : base + P->hp.step_of_node[node];
+  };
+  for (size_t s = 0; s < P->hp.steps.size(); ++s) {
+    left[s] = id(P->hp.steps[s].a);
+    right[s] = id(P->hp.steps[s].b);
+  }
+  return LF_OK;
+}
+
+lf_status lf_plan_steps(const lf_plan* P, int32_t* dims, double* macs, double* bytes) {
+  if (!P || (!dims && !P->hp.steps.empty())) return fail(LF_INVALID_ARGUMENT, "NULL argument");
+  for (size_t s = 0; s < P->hp.steps.size(); ++s) {
+    const lf::StepLayout& st = P->hp.steps[s];
+    int32_t* d = dims + 8 * s;
+    d[0] = st.nz; d[1] = st.nm; d[2] = st.nn; d[3] = st.nk;
+    d[4] = st.variant; d[5] = st.dtype; d[6] = P->store_dt[st.out]; d[7] = st.kernel;
+    if (macs) macs[s] = st.macs;
+    if (bytes) bytes[s] = st.bytes;
+  }
+  return LF_OK;
+}
+
+lf_status lf_plan_bind_workspace(lf_plan* P, void* dev_ptr, uint64_t bytes, void* stream) {
+  if (!P) return fail(LF_INVALID_ARGUMENT, "plan is NULL");
+  if (!dev_ptr) return fail(LF_INVALID_ARGUMENT, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % ALIGN) return fail(LF_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  if (bytes < P->ws_bytes) return fail(LF_OUT_OF_WORKSPACE, "workspace smaller than lf_plan_info.workspace_bytes");
+  hipStream_t st = as_stream(stream);
+  P->ws = static_cast<char*>(dev_ptr);
+  P->ws_size = bytes;
+  P->bound = false;
+  P->invariant_done = false;
+  P->calibrated = P->opts.dtype == LF_C64;
+  if (P->graph_exec) { (void)hipGraphExecDestroy(P->graph_exec); P->graph_exec = nullptr; }
+  if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+  // leaves: layout, exponent, rounding, upload
+  const int L = leaf_count(P);
+  std::vector<char> host;
+  int64_t lo = P->full_off[0], hi = 0;
+  for (int i = 0; i < L; ++i) {
+    int64_t b = P->elems[i] * (P->store_dt[i] ? 4 : 8);
+    int nsl = 0;
+    for (int x : P->hp.order[i])
+      if (std::find(P->hp.sliced.begin(), P->hp.sliced.end(), x) != P->hp.sliced.end()) nsl++;
+    hi = std::max(hi, P->full_off[i] + (b << nsl));
+  }
+  host.assign(size_t(hi - lo), 0);
+  std::vector<lf::cd> lay;
+  for (int i = 0; i < L; ++i) {
+    leaf_layout(P, i, lay);
+    char* dst = host.data() + (P->full_off[i] - lo);
+    if (P->store_dt[i] == 0) {
+      float* f = reinterpret_cast<float*>(dst);
+      for (size_t e = 0; e < lay.size(); ++e) { f[2 * e] = float(lay[e].real()); f[2 * e + 1] = float(lay[e].imag()); }
+      P->exp2[i] = 0;
+    } else {
+      double mx = 0;
+      for (auto& v : lay) mx = std::max(mx, std::max(std::fabs(v.real()), std::fabs(v.imag())));
+      int e = mx > 0 ? int(std::ceil(std::log2(mx))) - 12 : 0;
+      P->exp2[i] = e;
+      _Float16* h = reinterpret_cast<_Float16*>(dst);
+      for (size_t k = 0; k < lay.size(); ++k) {
+        h[2 * k] = (_Float16)float(std::ldexp(lay[k].real(), -e));
+        h[2 * k + 1] = (_Float16)float(std::ldexp(lay[k].imag(), -e));
+      }
+    }
+  }
+  if (P->opts.dtype == LF_C64) propagate_exponents(P);
+  HIPCHK(hipMemcpyAsync(P->ws + lo, host.data(), host.size(), hipMemcpyHostToDevice, st));
+  // gather tables
+  std::vector<std::vector<int64_t>> tabs;
+  for (size_t s = 0; s < P->hp.steps.size(); ++s) {
+    if (P->gtab_off[s] < 0) continue;
+    const lf::StepLayout& step = P->hp.steps[s];
+    const int64_t Z = int64_t(1) << step.nz;
+    std::vector<int64_t> t(2 * Z, 0);
+    auto fill = [&](const lf::Gather& g, int64_t block, int64_t* out) {
+      for (int64_t z = 0; z < Z; ++z) {
+        if (g.stored_batched) { out[z] = z * block; continue; }
+        const uint64_t cs = P->net.closed_padded[size_t(z)];
+        int64_t o = 0;
+        for (size_t i = 0; i < g.q.size(); ++i)
+          if ((cs >> g.q[i]) & 1) o += g.stride[i];
+        out[z] = o;
+      }
+    };
+    fill(step.ga, int64_t(1) << (step.nm + step.nk), t.data());
+    fill(step.gb, int64_t(1) << (step.nn + step.nk), t.data() + Z);
+    tabs.push_back(std::move(t));
+    HIPCHK(hipMemcpyAsync(P->ws + P->gtab_off[s], tabs.back().data(), 2 * Z * sizeof(int64_t),
+                          hipMemcpyHostToDevice, st));
+  }
+  if (!P->copies.empty())
+    HIPCHK(hipMemcpyAsync(P->ws + P->off_copies_tab, P->copies.data(),
+                          P->copies.size() * sizeof(lf::SliceCopy), hipMemcpyHostToDevice, st));
+  HIPCHK(lf::launch_zero_u32(reinterpret_cast<unsigned*>(P->ws + P->off_sat), 1, st));
+  HIPCHK(lf::launch_zero_u32(reinterpret_cast<unsigned*>(P->ws + P->off_amax),
+                             int64_t(std::max<size_t>(1, P->hp.steps.size())), st));
+  // host staging buffer must outlive the copy
+  HIPCHK(hipStreamSynchronize(st));
+  P->bound = true;
+  return LF_OK;
+}
+
+static lf_status ensure_ready(lf_plan* P, int64_t sigma, hipStream_t st) {
+  if (!P->calibrated) {
+    lf_status r = calibrate(P, sigma, st);
+    if (r) return r;
+  }
+  if (!P->invariant_done) {
+    for (int s : P->invariant_steps) {
+      lf_status r = run_step(P, s, st);
+      if (r) return r;
+    }
+    P->invariant_done = true;
+  }
+  return LF_OK;
+}
+
+static lf_status contract_graph(lf_plan* P, int64_t s0, int64_t count, double* out, hipStream_t st) {
+  const int G = P->opts.slices_per_graph;
+  int64_t* sigma_dev = reinterpret_cast<int64_t*>(P->ws + P->off_sigma);
+  if (!P->graph_exec || P->graph_out != out || P->graph_slices != G) {
+    if (P->graph_exec) { (void)hipGraphExecDestroy(P->graph_exec); P->graph_exec = nullptr; }
+    if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+    // the caller's stream may be the null stream, which cannot be captured:
+    // record on a private stream (nothing runs during capture), launch on st
+    if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = P->cap_stream;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    lf_status r = LF_OK;
+    for (int g = 0; g < G && r == LF_OK; ++g) {
+      r = run_slice(P, sigma_dev, 0, out, cs);
+      if (r == LF_OK && lf::launch_add_i64(sigma_dev, 1, cs) != hipSuccess)
+        r = fail(LF_HIP_ERROR, "graph capture: counter kernel");
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (r) { if (g) (void)hipGraphDestroy(g); return r; }
+    if (e != hipSuccess) return fail(LF_HIP_ERROR, std::string("end capture: ") + hipGetErrorString(e));
+    P->graph = g;
+    HIPCHK(hipGraphInstantiate(&P->graph_exec, g, nullptr, nullptr, 0));
+    P->graph_out = out;
+    P->graph_stream = st;
+    P->graph_slices = G;
+  }
+  int64_t done = 0;
+  HIPCHK(lf::launch_set_i64(sigma_dev, s0, st));
+  while (count - done >= G) {
+    HIPCHK(hipGraphLaunch(P->graph_exec, st));
+    done += G;
+  }
+  for (; done < count; ++done) {
+    lf_status r = run_slice(P, nullptr, s0 + done, out, st);
+    if (r) return r;
+  }
+  return LF_OK;
+}
+
+lf_status lf_contract_slices(lf_plan* P, int64_t s0, int64_t s1, void* out_amps, void* stream) {
+  if (!P) return fail(LF_INVALID_ARGUMENT, "plan is NULL");
+  if (!P->bound) return fail(LF_NOT_BOUND, "no workspace bound");
+  const int64_t ns = int64_t(1) << P->hp.sliced.size();
+  if (s0 < 0 || s1 < s0 || s1 > ns) return fail(LF_INVALID_ARGUMENT, "slice range outside [0, n_slices]");
+  if (s0 == s1) return LF_OK;
+  if (!out_amps) return fail(LF_INVALID_ARGUMENT, "out_amps is NULL");
+  hipStream_t st = as_stream(stream);
+  double* out = static_cast<double*>(out_amps);
+  lf_status r = ensure_ready(P, s0, st);
+  if (r) return r;
+  if (P->opts.launch_mode == LF_LAUNCH_GRAPH && (s1 - s0) >= P->opts.slices_per_graph) {
+    r = contract_graph(P, s0, s1 - s0, out, st);
+    if (r) return r;
+  } else {
+    for (int64_t s = s0; s < s1; ++s) {
+      r = run_slice(P, nullptr, s, out, st);
+      if (r) return r;
+    }
+  }
+  if (P->opts.check_overflow) {
+    unsigned sat = 0;
+    HIPCHK(hipMemcpyAsync(&sat, P->ws + P->off_sat, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (sat) {
+      HIPCHK(lf::launch_zero_u32(reinterpret_cast<unsigned*>(P->ws + P->off_sat), 1, st));
+      return fail(LF_OVERFLOW, "complex-half values saturated in the contracted range");
+    }
+  }
+  return LF_OK;
+}
+
+lf_status lf_postselect_topk(const void* amps, int64_t n_groups, int64_t group_size, int32_t k,
+                             int64_t* out_idx, double* out_prob, void* stream) {
+  if (n_groups < 0) return fail(LF_INVALID_ARGUMENT, "n_groups < 0");
+  if (n_groups == 0) return LF_OK;
+  if (!amps || !out_idx || !out_prob) return fail(LF_INVALID_ARGUMENT, "NULL pointer");
+  if (group_size < 1 || group_size > (int64_t(1) << 26)) return fail(LF_INVALID_ARGUMENT, "group_size out of range");
+  if (k < 1 || k > 1024 || k > group_size) return fail(LF_INVALID_ARGUMENT, "k out of range");
+  HIPCHK(lf::launch_topk(static_cast<const double*>(amps), n_groups, group_size, k, out_idx, out_prob,
+                         as_stream(stream)));
+  return LF_OK;
+}
+
+lf_status lf_profile_steps(lf_plan* P, int32_t reps, double* out_ms, void* stream) {
+  if (!P || !out_ms || reps < 1) return fail(LF_INVALID_ARGUMENT, "bad argument");
+  if (!P->bound) return fail(LF_NOT_BOUND, "no workspace bound");
+  hipStream_t st = as_stream(stream);
+  lf_status r = ensure_ready(P, 0, st);
+  if (r) return r;
+  HIPCHK(lf::launch_instantiate(reinterpret_cast<const lf::SliceCopy*>(P->ws + P->off_copies_tab),
+                                int(P->copies.size()), P->copy_max_n, P->ws, nullptr, 0, st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (size_t s = 0; s < P->hp.steps.size(); ++s) {
+    r = run_step(P, int(s), st);
+    if (r) break;
+    HIPCHK(hipEventRecord(e0, st));
+    for (int i = 0; i < reps && r == LF_OK; ++i) r = run_step(P, int(s), st);
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    out_ms[s] = double(ms) / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return r;
+}
+
+lf_status lf_contract_pair(int32_t dtype_in, int32_t dtype_out, int32_t kernel, const void* A,
+                           const void* B, void* C, int32_t nz, int32_t nm, int32_t nn, int32_t nk,
+                           const int64_t* c_strides, float scale, void* stream) {
+  if (!A || !B || !C || !c_strides) return fail(LF_INVALID_ARGUMENT, "NULL pointer");
+  if ((dtype_in != 0 && dtype_in != 1) || (dtype_out != 0 && dtype_out != 1))
+    return fail(LF_INVALID_ARGUMENT, "dtype must be LF_C64 or LF_CHALF");
+  if (nz < 0 || nm < 0 || nn < 0 || nk < 0 || nz > lf::MAXZ || nm > lf::MAXMN || nn > lf::MAXMN ||
+      nk > 40 || nz + nm + nk > 40 || nz + nn + nk > 40)
+    return fail(LF_INVALID_ARGUMENT, "sizes out of range");
+  if (reinterpret_cast<uintptr_t>(A) % 16 || reinterpret_cast<uintptr_t>(B) % 16)
+    return fail(LF_INVALID_ARGUMENT, "A and B must be 16-byte aligned");
+  if (kernel < -1 || kernel >= lf::K_COUNT) return fail(LF_INVALID_ARGUMENT, "kernel id");
+  lf::GettArgs a{};
+  a.A = A;
+  a.B = B;
+  a.C = C;
+  a.nz = nz;
+  a.nm = nm;
+  a.nn = nn;
+  a.nk = nk;
+  for (int i = 0; i < nz; ++i) a.cz[i] = c_strides[i];
+  for (int i = 0; i < nm; ++i) a.cm[i] = c_strides[nz + i];
+  for (int i = 0; i < nn; ++i) a.cn[i] = c_strides[nz + nm + i];
+  a.scale = scale;
+  if (kernel < 0)
+    kernel = lf::kernel_applicable(lf::K_MFMA, dtype_in, nz, nm, nn, nk) && nk >= 2 ? lf::K_MFMA : lf::K_THIN;
+  HIPCHK(lf::launch_gett(kernel, dtype_in, dtype_out, a, as_stream(stream)));
+  return LF_OK;
+}
+
+void lf_plan_destroy(lf_plan* P) { delete P; }
+
+}  // extern "C"

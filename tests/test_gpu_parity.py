@@ -1,0 +1,342 @@
+"""Parity of the HIP path against the oracle, through the C ABI.
+
+Tolerances (norm-wise relative error over the whole output, ||a - ref|| /
+||ref||): complex64 1e-5; complex-half 5e-3 with fidelity overlap >= 0.999.
+Top-k: bit-exact against the oracle's selection on the same amplitudes.
+"""
+
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import sv, tn, topk
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_built")]
+
+torch = pytest.importorskip("torch")
+
+C64_TOL = 1e-5
+CHALF_TOL = 5e-3
+
+
+def _say(msg):
+    sys.stdout.write(msg + "\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_18889_amd as lf
+    from paper_2406_18889_amd import _lib
+    _lib.load()  # fails loudly if the library is missing
+    return lf
+
+
+def rel_err(a, ref):
+    a = np.asarray(a).reshape(-1)
+    ref = np.asarray(ref).reshape(-1)
+    return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+
+
+def fidelity(a, ref):
+    a = np.asarray(a).reshape(-1)
+    ref = np.asarray(ref).reshape(-1)
+    return float(abs(np.vdot(ref, a)) ** 2 / (np.vdot(a, a).real * np.vdot(ref, ref).real))
+
+
+# ------------------------------------------------------------- kernel pairs
+def _ref_pair(A, B, nz, nm, nn, nk):
+    Z, M, N, K = 1 << nz, 1 << nm, 1 << nn, 1 << nk
+    a = A.reshape(Z, M, K).astype(np.complex128)
+    b = B.reshape(Z, N, K).astype(np.complex128)
+    return np.matmul(a, np.transpose(b, (0, 2, 1)))  # [Z, M, N]
+
+
+def _rand_strides(nz, nm, nn, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    perm = rng.permutation(nz + nm + nn)
+    return (1 << perm).astype(np.int64)  # bit b of the concatenated (z, m, n) -> stride
+
+
+def _scatter(ref, nz, nm, nn, strides):
+    Z, M, N = 1 << nz, 1 << nm, 1 << nn
+    out = np.zeros(Z * M * N, np.complex128)
+    z = np.arange(Z)[:, None, None]
+    m = np.arange(M)[None, :, None]
+    n = np.arange(N)[None, None, :]
+    off = np.zeros((Z, M, N), np.int64)
+    for b in range(nz):
+        off += ((z >> b) & 1) * strides[b]
+    for b in range(nm):
+        off += ((m >> b) & 1) * strides[nz + b]
+    for b in range(nn):
+        off += ((n >> b) & 1) * strides[nz + nm + b]
+    out[off.reshape(-1)] = ref.reshape(-1)
+    return out
+
+
+SHAPES = [
+    # nz, nm, nn, nk: thin, tails below a tile, multi-tile, batch, K = 1
+    (0, 10, 2, 2), (0, 3, 1, 0), (2, 6, 5, 3), (0, 8, 7, 6), (3, 7, 6, 5),
+    (0, 9, 6, 9), (1, 4, 4, 1), (0, 5, 4, 4), (0, 12, 8, 4),
+]
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_pair_c64(lf, kernel, shape):
+    nz, nm, nn, nk = shape
+    if kernel == 1 and not (nm >= 5 and nn >= 4):
+        pytest.skip("MFMA tile needs nm >= 5 and nn >= 4")
+    _say(f"pair c64 kernel={kernel} shape={shape}")
+    A = wl.random_complex((1 << (nz + nm + nk),), seed=1 + sum(shape)).astype(np.complex64)
+    B = wl.random_complex((1 << (nz + nn + nk),), seed=2 + sum(shape)).astype(np.complex64)
+    st = _rand_strides(nz, nm, nn, seed=3 + sum(shape))
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    dC = torch.zeros(1 << (nz + nm + nn), dtype=torch.complex64, device="cuda")
+    lf.contract_pair(dA, dB, dC, nz, nm, nn, nk, st, 1.0, kernel)
+    torch.cuda.synchronize()
+    ref = _scatter(_ref_pair(A, B, nz, nm, nn, nk), nz, nm, nn, st)
+    assert rel_err(dC.cpu().numpy(), ref) < C64_TOL
+
+
+def _to_half_pairs(x, e):
+    v = np.stack([x.real, x.imag], -1) * 2.0 ** (-e)
+    return torch.from_numpy(v.astype(np.float16)).cuda()
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_pair_chalf(lf, kernel, shape):
+    nz, nm, nn, nk = shape
+    if kernel == 1 and not (nm >= 5 and nn >= 4):
+        pytest.skip("MFMA tile needs nm >= 5 and nn >= 4")
+    _say(f"pair chalf kernel={kernel} shape={shape}")
+    A = wl.random_complex((1 << (nz + nm + nk),), seed=11 + sum(shape))
+    B = wl.random_complex((1 << (nz + nn + nk),), seed=12 + sum(shape))
+    st = _rand_strides(nz, nm, nn, seed=13 + sum(shape))
+    dA = _to_half_pairs(A, -8)
+    dB = _to_half_pairs(B, -8)
+    # stored A, B are value * 2^8; result scaled back by 2^-16 into half range
+    dC = torch.zeros((1 << (nz + nm + nn), 2), dtype=torch.float16, device="cuda")
+    lf.contract_pair(dA, dB, dC, nz, nm, nn, nk, st, 2.0 ** -16 * 64, kernel)
+    torch.cuda.synchronize()
+    Ah = (dA.cpu().numpy().astype(np.float64) @ np.array([1, 1j])) * 2.0 ** -8
+    Bh = (dB.cpu().numpy().astype(np.float64) @ np.array([1, 1j])) * 2.0 ** -8
+    ref = _scatter(_ref_pair(Ah, Bh, nz, nm, nn, nk), nz, nm, nn, st) * 64
+    got = dC.cpu().numpy().astype(np.float64) @ np.array([1, 1j])
+    # inputs exact in both; the only roundings are fp32 accumulation and the
+    # final fp16 store
+    assert rel_err(got, ref) < 2e-3
+
+
+def test_pair_half_in_c64_out(lf):
+    nz, nm, nn, nk = 0, 7, 5, 6
+    A = wl.random_complex((1 << (nm + nk),), seed=21)
+    B = wl.random_complex((1 << (nn + nk),), seed=22)
+    st = _rand_strides(nz, nm, nn, seed=23)
+    dA, dB = _to_half_pairs(A, 0), _to_half_pairs(B, 0)
+    dC = torch.zeros(1 << (nm + nn), dtype=torch.complex64, device="cuda")
+    lf.contract_pair(dA, dB, dC, nz, nm, nn, nk, st, 1.0, 1)
+    torch.cuda.synchronize()
+    Ah = dA.cpu().numpy().astype(np.float64) @ np.array([1, 1j])
+    Bh = dB.cpu().numpy().astype(np.float64) @ np.array([1, 1j])
+    ref = _scatter(_ref_pair(Ah, Bh, nz, nm, nn, nk), nz, nm, nn, st)
+    assert rel_err(dC.cpu().numpy(), ref) < 1e-5
+
+
+# ---------------------------------------------------------- whole circuits
+def test_rqc12_full_amplitudes_c64(lf):
+    """Configuration 1: 12 qubits, 8 cycles, all open, no slicing."""
+    _say("rqc12 c64")
+    c, o, cb, spec = wl.standard_workload("rqc12")
+    ref = sv.group_amplitudes(c, o, cb)
+    plan = lf.Plan(c, o, cb, max_log2=spec["max_log2"]).bind()
+    out = plan.contract(0, plan.info()["n_slices"])
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert got.shape == (1, 4096)
+    assert rel_err(got, ref) < C64_TOL
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_rqc12_other_seeds(lf, seed):
+    c = wl.random_circuit(3, 4, 8, seed)
+    o = np.arange(12)
+    cb = np.zeros(1, np.uint64)
+    ref = sv.group_amplitudes(c, o, cb)
+    plan = lf.Plan(c, o, cb, max_log2=20).bind()
+    got = plan.contract(0, plan.info()["n_slices"]).cpu().numpy()
+    assert rel_err(got, ref) < C64_TOL
+
+
+def _small_sliced(lf, dtype="c64", launch="stream", n_batch=16, chalf_min=16):
+    c = wl.random_circuit(4, 4, 10, seed=77)
+    o = [12, 13, 14, 15]
+    cb = wl.closed_bitstrings(16, o, n_batch, seed=5)
+    wires = tn.wire_list(tn.canonical_network(c, o, cb))
+    mid = [w for w in wires if w[1] == 3][:4]
+    plan = lf.Plan(c, o, cb, dtype=dtype, max_log2=20, sliced_wires=mid, launch=launch,
+                   slices_per_graph=4, chalf_min_log2=chalf_min).bind()
+    return c, o, cb, mid, plan
+
+
+def test_slices_match_projector_state_vector(lf):
+    """Each slice equals the state vector with projectors on the sliced wires;
+    the full range equals the exact amplitudes (slicing identity)."""
+    c, o, cb, mid, plan = _small_sliced(lf)
+    assert plan.sliced_wires() == mid
+    total = np.zeros((len(cb), 1 << len(o)), np.complex128)
+    for s in range(16):
+        _say(f"slice {s}")
+        got = plan.contract(s, s + 1).cpu().numpy()
+        v = tn.slice_values(s, 4)
+        ref = sv.group_amplitudes(c, o, cb, [(q, j, x) for (q, j), x in zip(mid, v)])
+        assert rel_err(got, ref) < C64_TOL
+        total += got
+    exact = sv.group_amplitudes(c, o, cb)
+    assert rel_err(total, exact) < C64_TOL
+    full = plan.contract(0, 16).cpu().numpy()
+    assert rel_err(full, exact) < C64_TOL
+
+
+def test_slice_additivity_and_determinism(lf):
+    _, _, _, _, plan = _small_sliced(lf)
+    a = plan.contract(0, 16)
+    b = plan.new_amplitudes()
+    plan.contract(0, 5, b)
+    plan.contract(5, 11, b)
+    plan.contract(11, 16, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    c2 = plan.contract(0, 16)
+    assert torch.equal(a, c2)
+    empty = plan.contract(3, 3)
+    assert torch.count_nonzero(empty).item() == 0
+
+
+def test_graph_launch_matches_stream(lf):
+    _, _, _, _, p1 = _small_sliced(lf, launch="stream")
+    _, _, _, _, p2 = _small_sliced(lf, launch="graph")
+    a = p1.contract(0, 16)
+    b = p2.contract(0, 16)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    # replay again (graph reuse) with eager work between replays
+    b2 = p2.new_amplitudes()
+    p2.contract(0, 9, b2)
+    torch.cuda.synchronize()
+    p2.contract(9, 16, b2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b2)
+
+
+def test_complex_half_small(lf):
+    c, o, cb, mid, plan = _small_sliced(lf, dtype="chalf", chalf_min=6)
+    assert plan.info()["n_half_steps"] > 0
+    got = plan.contract(0, 16).cpu().numpy()
+    exact = sv.group_amplitudes(c, o, cb)
+    e = rel_err(got, exact)
+    f = fidelity(got, exact)
+    _say(f"chalf small rel_err={e:.2e} fidelity={f:.6f}")
+    assert e < CHALF_TOL
+    assert f >= 0.999
+
+
+def test_rqc12_complex_half(lf):
+    c, o, cb, spec = wl.standard_workload("rqc12")
+    ref = sv.group_amplitudes(c, o, cb)
+    plan = lf.Plan(c, o, cb, dtype="chalf", max_log2=spec["max_log2"], chalf_min_log2=4).bind()
+    got = plan.contract(0, 1).cpu().numpy()
+    e, f = rel_err(got, ref), fidelity(got, ref)
+    _say(f"rqc12 chalf rel_err={e:.2e} fidelity={f:.6f}")
+    assert e < CHALF_TOL and f >= 0.999
+
+
+# -------------------------------------------------------------------- top-k
+@pytest.mark.parametrize("gs,k", [(64, 1), (64, 7), (1024, 1), (1024, 33), (256 * 64, 100)])
+def test_topk_bit_exact(lf, gs, k):
+    rng = np.random.Generator(np.random.PCG64(gs + k))
+    n = 256 * 64 if gs <= 256 * 64 else gs
+    n = max(n, gs)
+    a = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) / 64
+    # planted ties: duplicated values inside groups
+    a[5::97] = a[3]
+    d = torch.from_numpy(a).cuda()
+    idx, prob = lf.postselect_topk(d, gs, k)
+    i_ref, p_ref = topk.topk(a, gs, k)
+    assert np.array_equal(idx.cpu().numpy(), i_ref)
+    assert np.array_equal(prob.cpu().numpy(), p_ref)
+
+
+def test_topk_on_contracted_amplitudes(lf):
+    c, o, cb, mid, plan = _small_sliced(lf)
+    amps = plan.contract(0, 16)
+    idx, prob = lf.postselect_topk(amps, 16, 1)
+    i_ref, p_ref = topk.topk(amps.cpu().numpy(), 16, 1)
+    assert np.array_equal(idx.cpu().numpy(), i_ref)
+    assert np.array_equal(prob.cpu().numpy(), p_ref)
+
+
+# ------------------------------------------------------------- 30 qubits
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rqc30_plan(lf, dtype="c64", **kw):
+    from tests.golden.make_rqc30 import RQC30_SLICED_WIRES
+    c, o, cb, spec = wl.standard_workload("rqc30")
+    plan = lf.Plan(c, o, cb, dtype=dtype, max_log2=spec["max_log2"],
+                   sliced_wires=RQC30_SLICED_WIRES, **kw).bind()
+    return plan
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "rqc30_exact.npy")),
+                    reason="30-qubit oracle values not generated")
+def test_rqc30_full_sum_c64(lf):
+    """Configuration 2: 30 qubits, 14 cycles, 6 open, 256 closed strings,
+    2^8 slices; the sum of all slices equals the state vector."""
+    _say("rqc30 c64 full")
+    ref = np.load(os.path.join(GOLD, "rqc30_exact.npy"))
+    plan = _rqc30_plan(lf)
+    assert plan.info()["n_slices"] == 256
+    got = plan.contract(0, 256).cpu().numpy()
+    assert rel_err(got, ref) < C64_TOL
+    idx, _ = lf.postselect_topk(plan.contract(0, 256), 64, 1)
+    i_ref, _ = topk.topk(ref, 64, 1)
+    # selection from c64 amplitudes agrees with the exact one except where
+    # the two largest probabilities are within the error bound
+    p = topk.probabilities(ref)
+    agree = idx.cpu().numpy()[:, 0] == i_ref[:, 0]
+    for g in np.nonzero(~agree)[0]:
+        top2 = np.sort(p[g])[-2:]
+        assert top2[1] - top2[0] <= 4 * C64_TOL * top2[1]
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "rqc30_prefix_D1.npy")),
+                    reason="30-qubit prefix oracle values not generated")
+@pytest.mark.parametrize("D", [1, 2, 3, 4, 5])
+def test_rqc30_prefix_partial_sums(lf, D):
+    """A slice prefix [0, 2^(8-D)) equals the state vector with the D
+    most significant sliced wires projected on 0 (fraction f = 2^-D)."""
+    ref = np.load(os.path.join(GOLD, f"rqc30_prefix_D{D}.npy"))
+    plan = _rqc30_plan(lf)
+    got = plan.contract(0, 1 << (8 - D)).cpu().numpy()
+    assert rel_err(got, ref) < C64_TOL
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "rqc30_exact.npy")),
+                    reason="30-qubit oracle values not generated")
+def test_rqc30_full_sum_complex_half(lf):
+    ref = np.load(os.path.join(GOLD, "rqc30_exact.npy"))
+    plan = _rqc30_plan(lf, dtype="chalf")
+    got = plan.contract(0, 256).cpu().numpy()
+    e, f = rel_err(got, ref), fidelity(got, ref)
+    _say(f"rqc30 chalf rel_err={e:.2e} fidelity={f:.6f} half_steps={plan.info()['n_half_steps']}")
+    assert e < CHALF_TOL and f >= 0.999

@@ -212,9 +212,9 @@ def closed_bitstrings(n_qubits: int, open_qubits: Sequence[int], n_batch: int,
 # the circuits are seeded stand-ins, not the Sycamore circuit files.
 WORKLOADS = {
     "rqc12": dict(rows=3, cols=4, cycles=8, n_removed=0, n_open=12, n_batch=1,
-                  n_sliced=0, max_log2=40),
+                  n_sliced=0, max_log2=30),
     "rqc30": dict(rows=5, cols=6, cycles=14, n_removed=0, n_open=6, n_batch=256,
-                  n_sliced=8, max_log2=40),
+                  n_sliced=8, max_log2=26),
     "rqc53": dict(rows=6, cols=9, cycles=20, n_removed=1, n_open=10, n_batch=256,
                   n_sliced=-1, max_log2=28),
 }
