@@ -21,6 +21,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MI355X = {"hbm_gbs": 8000.0, "fp16_tflops": 2500.0, "fp32_tflops": 157.3}
+KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big"}
+# planner settings per workload (search effort, not inputs)
+PLAN_OPTS = {"rqc53": {"sa_iters": 4_000_000}}
 
 
 def parse():
@@ -28,50 +31,64 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rqc30")
-    ap.add_argument("--dtype", default="c64")
+    ap.add_argument("--workload", default="rqc53")
+    ap.add_argument("--dtype", default="chalf")
+    ap.add_argument("--compare", default="c64", help="second dtype timed on the same slices")
     ap.add_argument("--slices-per-step", type=int, default=16)
     ap.add_argument("--launch", default="stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--dump-steps", default="", help="write per-step shapes and times (json)")
     return ap.parse_args()
 
 
 def cpu_baseline(plan, circ, openq, cb, seconds):
-    """The oracle's complex128 contraction of slice 0 along the plan's tree,
-    run for about `seconds` of host time; the fraction of the slice's
-    multiply-adds done per second is reported as slices/s."""
+    """The oracle's complex128 contraction of slice 0 for one closed string,
+    along the plan's tree, run for about `seconds` of host time.  Its
+    multiply-add rate extrapolates to the whole slice; one slice of the
+    workload is that work for every closed string (the oracle handles one
+    string at a time at this size)."""
     import numpy as np
     from oracle import tn
 
     leaf_canon, steps, base = plan.tree()
     wires = plan.sliced_wires()
-    dims, macs, _ = plan.steps()
-    t0 = time.time()
-    leaves = tn.canonical_network(circ, openq, cb)
+    leaves = tn.canonical_network(circ, openq, cb[:1])
     if wires:
         leaves = tn.fix_wires(leaves, wires, tn.slice_values(0, len(wires)))
     keep = tn._keep_labels(openq)
+    # dry run over shapes: the oracle's own multiply-adds per step
+    shapes = {k: dict(zip(l, d.shape)) for k, (l, d) in leaves.items()}
+    work = []
+    for i, (a, b) in enumerate(steps):
+        da, db = shapes.pop(a), shapes.pop(b)
+        u = dict(da)
+        u.update(db)
+        work.append(float(np.prod(list(u.values()), dtype=np.float64)))
+        shapes[base + i] = {x: v for x, v in u.items() if not (x in da and x in db) or x in keep}
+    total = sum(work)
     nodes = dict(leaves)
-    done = 0.0
-    n_done = 0
+    done, n_done = 0.0, 0
     t_start = time.time()
     for i, (a, b) in enumerate(steps):
+        el = time.time() - t_start
+        if n_done > 0 and el > 0.5:
+            rate = done / el
+            if el + work[i] / rate > seconds:
+                break
         la, A = nodes.pop(a)
         lb, B = nodes.pop(b)
         nodes[base + i] = tn.contract_pair(la, A, lb, B, keep)
-        done += macs[i]
+        done += work[i]
         n_done += 1
-        if time.time() - t_start > seconds:
-            break
     el = time.time() - t_start
-    per_slice = float(macs.sum())
-    frac = done / per_slice
-    return {"value": frac / el, "unit": "slices/s", "cores": len(os.sched_getaffinity(0)),
-            "kind": "oracle",
-            "sample": f"complex128 numpy contraction of slice 0 along the plan's tree, "
-                      f"{n_done}/{len(steps)} steps = {frac:.3g} of the slice's multiply-adds "
-                      f"in {el:.1f} s (network build {t_start - t0:.1f} s excluded)"}
+    est_slice = el * total / done
+    return {"value": 1.0 / (est_slice * len(cb)), "unit": "slices/s",
+            "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+            "sample": f"complex128 numpy contraction of slice 0 for 1 of {len(cb)} closed strings "
+                      f"along the plan's tree: {n_done}/{len(steps)} steps = {done / total:.3g} "
+                      f"of its multiply-adds in {el:.1f} s; slice time extrapolated by "
+                      f"multiply-adds and multiplied by {len(cb)} strings"}
 
 
 def main():
@@ -87,10 +104,13 @@ def main():
 
     torch.cuda.set_device(0)
     circ, openq, cb, spec = wl.standard_workload(args.workload)
-    kw = {}
+    kw = dict(PLAN_OPTS.get(args.workload, {}))
     if args.workload == "rqc30":
         from tests.golden.make_rqc30 import RQC30_SLICED_WIRES
         kw["sliced_wires"] = RQC30_SLICED_WIRES
+    # both arithmetics search with the complex-half step costs, so they share
+    # one tree and one slicing (slice s is the same sub-network in both)
+    kw["search_dtype"] = "chalf"
     plan = lf.Plan(circ, openq, cb, dtype=args.dtype, max_log2=spec["max_log2"],
                    launch=args.launch, check_overflow=False, **kw)
     info = plan.info()
@@ -141,9 +161,13 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
     roof["kernel"] = {"step": dom, "nz_nm_nn_nk": [int(x) for x in dims[dom, :4]],
-                      "kind": "mfma" if dims[dom, 7] == 1 else "thin",
+                      "kind": KERNEL_NAMES.get(int(dims[dom, 7]), "?"),
                       "ms": float(ms[dom]), "share_of_slice": float(share[dom] / share.sum())}
 
+    if args.dump_steps:
+        with open(args.dump_steps, "w") as f:
+            json.dump({"dims": dims.tolist(), "macs": macs.tolist(), "bytes": byts.tolist(),
+                       "ms": [float(x) for x in ms]}, f)
     per_slice_flops = 8.0 * info["macs_per_slice"]
     out = {
         "metric": "sliced-subtask contractions/s",
@@ -168,6 +192,40 @@ def main():
         "macs_per_slice": info["macs_per_slice"],
         "roofline": roof,
     }
+    if args.compare and args.compare not in ("none", args.dtype):
+        # the other arithmetic on the same slices: throughput and agreement
+        other = lf.Plan(circ, openq, cb, dtype=args.compare, max_log2=spec["max_log2"],
+                        launch=args.launch, check_overflow=False, **kw)
+        if other.sliced_wires() != plan.sliced_wires():
+            raise RuntimeError("the two arithmetics planned different slicings")
+        other.bind()
+        ref = other.new_amplitudes()
+        other.contract(0, 1, ref)
+        torch.cuda.synchronize()
+        n_cmp = max(1, min(args.steps, 4))
+        t1 = time.perf_counter()
+        done_o = 0
+        for i in range(n_cmp):
+            s0 = ((args.warmup + i) * S) % n_slices
+            s1 = min(s0 + S, n_slices)
+            other.contract(s0, s1, ref)
+            done_o += s1 - s0
+        torch.cuda.synchronize()
+        v_other = done_o / (time.perf_counter() - t1)
+        # agreement over slices [0, S): both dtypes, fresh accumulators
+        a1 = plan.new_amplitudes()
+        plan.contract(0, S, a1)
+        a2 = other.new_amplitudes()
+        other.contract(0, S, a2)
+        torch.cuda.synchronize()
+        x, y = a1.cpu().numpy().reshape(-1), a2.cpu().numpy().reshape(-1)
+        rel = float(np.linalg.norm(x - y) / np.linalg.norm(y))
+        fid = float(abs(np.vdot(y, x)) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real))
+        out["compare"] = {"dtype": args.compare, "value": v_other, "unit": "slices/s",
+                          "speedup": value / v_other,
+                          "agreement_slices": [0, S], "rel_err_vs_compare": rel,
+                          "fidelity_vs_compare": fid}
+        del other
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(plan, circ, openq, cb, args.cpu_seconds)
     print(json.dumps(out))

@@ -89,6 +89,12 @@ typedef struct lf_plan_opts {
   int32_t check_overflow;        /* nonzero: lf_contract_slices synchronizes at its end
                                     and reports LF_OVERFLOW on saturation */
   int32_t slices_per_graph;      /* graph mode: slices captured per graph replay */
+  int32_t search_dtype;          /* arithmetic whose step costs the search minimises;
+                                    -1 = dtype.  Two plans that differ only in dtype and
+                                    share search_dtype get the same tree and slices */
+  int32_t autotune;              /* nonzero: the first contraction times every applicable
+                                    kernel variant (tile shape) per step shape and keeps
+                                    the fastest; results are shared by the process */
 } lf_plan_opts;
 
 typedef struct lf_plan_info {
@@ -116,7 +122,7 @@ typedef struct lf_plan lf_plan;
 
 /* Defaults: LF_C64, cap 2^28, planner-chosen slices, FLOP+memory cost,
  * 8 greedy and 64 partition trials, no annealing, seed 1, chalf_min_log2 16,
- * stream launch,
+ * stream launch, autotuning on,
  * overflow check on, 8 slices per graph. */
 void lf_plan_opts_default(lf_plan_opts* opts);
 
@@ -214,6 +220,57 @@ lf_status lf_profile_steps(lf_plan* plan, int32_t reps, double* out_ms, void* st
 lf_status lf_contract_pair(int32_t dtype_in, int32_t dtype_out, int32_t kernel, const void* A,
                            const void* B, void* C, int32_t nz, int32_t nm, int32_t nn, int32_t nk,
                            const int64_t* c_strides, float scale, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned step-cost model (planner extension): a three-layer perceptron
+ * in -> H -> H -> 1 with ReLU on both hidden layers, float32, regressing the
+ * log of a contraction step's run time from LF_N_FEATURES features of the
+ * step's shape; fitted by mean squared error with Adam.  The parameters are
+ * one float32 device array: W1 [in][H] row-major, b1 [H], W2 [H][H], b2 [H],
+ * W3 [H], b3 [1].  All arrays here are caller-owned device memory.
+ * ---------------------------------------------------------------------- */
+#define LF_N_FEATURES 14
+
+/* Features of a step over 2^nz x 2^nm x 2^nn x 2^nk (see lf_plan_steps) in
+ * arithmetic dtype: nz, nm, nn, nk, log2 of multiply-adds, log2 sizes of A,
+ * B and C, log2 bytes, log2 arithmetic intensity, dtype, MFMA-tile flag,
+ * batched flag, log2 roofline microseconds.  Host only.  out[LF_N_FEATURES]. */
+lf_status lf_step_features(int32_t nz, int32_t nm, int32_t nn, int32_t nk, int32_t dtype,
+                           float* out);
+
+/* Parameter count and workspace bytes for batches up to max_batch. */
+lf_status lf_mlp_sizes(int32_t n_in, int32_t hidden, int64_t max_batch, int64_t* n_params,
+                       uint64_t* workspace_bytes);
+
+/* Y[batch] = network(X[batch][n_in]).  Asynchronous on stream. */
+lf_status lf_mlp_forward(const float* params, int32_t n_in, int32_t hidden, const float* X,
+                         int64_t batch, float* Y, void* workspace, uint64_t workspace_bytes,
+                         void* stream);
+
+/* loss[0] = mean((Y - T)^2) and grads[n_params] = its gradient (same layout
+ * as params), for one batch.  Asynchronous on stream. */
+lf_status lf_mlp_gradients(const float* params, int32_t n_in, int32_t hidden, const float* X,
+                           const float* T, int64_t batch, float* grads, float* loss,
+                           void* workspace, uint64_t workspace_bytes, void* stream);
+
+/* One Adam update (step counts from 1) of params with moments m, v. */
+lf_status lf_mlp_adam_step(float* params, float* m, float* v, const float* grads, int64_t n_params,
+                           int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Loads a trained network (host copy of params, n_in == LF_N_FEATURES) with
+ * its feature standardisation (x - x_mean[i]) / x_std[i] and target
+ * log(seconds) = y * y_std + y_mean, for plans built with LF_COST_MLP.  Such
+ * plans evaluate it on the current device with lf_mlp_forward, once per
+ * batch exponent, over every step shape the search can meet (a host table
+ * of predicted seconds); lf_build_network then needs a GPU. */
+lf_status lf_costmodel_load(const float* params, int32_t n_in, int32_t hidden, const float* x_mean,
+                            const float* x_std, float y_mean, float y_std);
+lf_status lf_costmodel_clear(void);
+
+/* Predicted seconds of one step under the loaded model (tabulates on first
+ * use of nz).  Errors: LF_INVALID_ARGUMENT when no model is loaded. */
+lf_status lf_costmodel_predict(int32_t nz, int32_t nm, int32_t nn, int32_t nk, int32_t dtype,
+                               double* seconds);
 
 void lf_plan_destroy(lf_plan* plan);
 

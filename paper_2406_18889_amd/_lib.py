@@ -27,6 +27,7 @@ LF_COST_FLOPMEM = 0
 LF_COST_MLP = 1
 LF_LAUNCH_STREAM = 0
 LF_LAUNCH_GRAPH = 1
+LF_N_FEATURES = 14
 
 
 class lf_gate(ctypes.Structure):
@@ -47,7 +48,8 @@ class lf_plan_opts(ctypes.Structure):
                 ("sa_iters", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("chalf_min_log2", ctypes.c_int32),
                 ("launch_mode", ctypes.c_int32), ("check_overflow", ctypes.c_int32),
-                ("slices_per_graph", ctypes.c_int32)]
+                ("slices_per_graph", ctypes.c_int32), ("search_dtype", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class lf_plan_info(ctypes.Structure):
@@ -84,6 +86,20 @@ SIGNATURES = {
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                           ctypes.c_float, _P]),
+    "lf_step_features": (ctypes.c_int32, [ctypes.c_int32] * 5 + [ctypes.POINTER(ctypes.c_float)]),
+    "lf_mlp_sizes": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]),
+    "lf_mlp_forward": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P,
+                                        ctypes.c_uint64, _P]),
+    "lf_mlp_gradients": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64, _P,
+                                          _P, _P, ctypes.c_uint64, _P]),
+    "lf_mlp_adam_step": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
+                                          ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
+    "lf_costmodel_load": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_float), ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                           ctypes.c_float, ctypes.c_float]),
+    "lf_costmodel_clear": (ctypes.c_int32, []),
+    "lf_costmodel_predict": (ctypes.c_int32, [ctypes.c_int32] * 5 + [ctypes.POINTER(ctypes.c_double)]),
     "lf_plan_destroy": (None, [_P]),
     "lf_last_error": (ctypes.c_char_p, []),
 }

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libleapfrog.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["network.cpp", "planner.cpp", "costmodel.cpp", "kernels.hip", "runtime.hip",
+SOURCES = ["network.cpp", "planner.cpp", "costmodel.hip", "kernels.hip", "runtime.hip",
            "mlp.hip"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

@@ -38,10 +38,14 @@ struct GettArgs {
   int64_t cn[MAXMN];
 };
 
-enum KernelId : int { K_THIN = 0, K_MFMA = 1, K_MFMA_SMALLK = 2, K_COUNT = 3 };
+// K_THIN: streaming, one row per thread; K_MFMA: 128 x 64 complex tile (both
+// arithmetics); K_MFMA_BIG: 256 x 64 complex tile, complex-half only.
+enum KernelId : int { K_THIN = 0, K_MFMA = 1, K_MFMA_BIG = 2, K_COUNT = 3 };
 
-// in_dt / out_dt: 0 complex64 (float pairs), 1 complex-half (_Float16 pairs)
-hipError_t launch_gett(int kernel, int in_dt, int out_dt, const GettArgs& a, hipStream_t s);
+// a_dt, b_dt, out_dt: 0 complex64 (float pairs), 1 complex-half (_Float16
+// pairs).  a_dt != b_dt is allowed only as a complex-half A with a
+// complex64 B, on the streaming kernel.
+hipError_t launch_gett(int kernel, int a_dt, int b_dt, int out_dt, const GettArgs& a, hipStream_t s);
 bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk);
 
 // Copies of the slice-dependent blocks of leaf tensors.

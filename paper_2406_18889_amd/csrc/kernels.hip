@@ -16,6 +16,7 @@
 
 #include <cfloat>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -85,7 +86,7 @@ __device__ __forceinline__ void block_amax_sat(float local_max, unsigned local_s
 // steps with a narrow side (a large tensor against a gate or small branch),
 // which are bound by HBM traffic: every A element is read once, every C
 // element written once.
-template <typename TI, typename TO>
+template <typename TA, typename TB, typename TO>
 __global__ void __launch_bounds__(256) gett_thin(GettArgs a) {
   constexpr int NB = 8;
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
@@ -93,8 +94,8 @@ __global__ void __launch_bounds__(256) gett_thin(GettArgs a) {
   __shared__ int64_t cnT[256];
   for (int n = threadIdx.x; n < N && n < 256; n += blockDim.x) cnT[n] = scatter_bits(n, a.cn, a.nn);
   __syncthreads();
-  const TI* A = static_cast<const TI*>(a.A);
-  const TI* B = static_cast<const TI*>(a.B);
+  const TA* A = static_cast<const TA*>(a.A);
+  const TB* B = static_cast<const TB*>(a.B);
   TO* C = static_cast<TO*>(a.C);
   float lmax = 0.0f;
   unsigned lsat = 0;
@@ -110,12 +111,12 @@ __global__ void __launch_bounds__(256) gett_thin(GettArgs a) {
       for (int j = 0; j < NB; ++j) { cr[j] = 0.0f; ci[j] = 0.0f; }
       for (int64_t k = 0; k < K; ++k) {
         float ar, ai;
-        CIO<TI>::load(A, arow + k, ar, ai);
+        CIO<TA>::load(A, arow + k, ar, ai);
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
           if (n0 + j < N) {
             float br, bi;
-            CIO<TI>::load(B, bz + (n0 + j) * K + k, br, bi);
+            CIO<TB>::load(B, bz + (n0 + j) * K + k, br, bi);
             cr[j] += ar * br - ai * bi;
             ci[j] += ar * bi + ai * br;
           }
@@ -307,33 +308,194 @@ __global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
   block_amax_sat(lmax, lsat, a.amax, a.sat);
 }
 
+// ------------------------------------------------ MFMA, large f16 tile
+// Complex-half operands, block tile 256 (m) x 64 (complex n) x 32 (complex
+// k); waves 2 (m) x 2 (n); each wave owns 4 x 2 MFMA 32x32x16 blocks
+// (128 m x 64 rows of B').  Both LDS tiles hold plain (re, im) rows; the B'
+// fragment of a lane is formed in registers from 4 complex values of row
+// n = n'/2: row 2n gets (Br, -Bi), row 2n+1 gets (Bi, Br).  The next K tile
+// is fetched from HBM into registers while the current one is multiplied.
+constexpr int BG_BM = 256, BG_BN = 64, BG_BK = 32;
+constexpr int BG_LDK = 2 * BG_BK + 8;  // halves per LDS row (16 B pad)
+
+__device__ __forceinline__ f16x8 bprime_frag(uint4 raw, int parity) {
+  uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    w[i] = parity ? ((w[i] >> 16) | (w[i] << 16)) : (w[i] ^ 0x80000000u);
+  f16x8 r;
+  __builtin_memcpy(&r, w, 16);
+  return r;
+}
+
+template <typename TO>
+__global__ void __launch_bounds__(256, 2) gett_mfma_big(GettArgs a) {
+  __shared__ __attribute__((aligned(16))) _Float16 sA[BG_BM * BG_LDK];
+  __shared__ __attribute__((aligned(16))) _Float16 sB[BG_BN * BG_LDK];
+  __shared__ int64_t cmT[BG_BM];
+  __shared__ int64_t cnT[BG_BN];
+
+  const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
+  const int64_t mt = (M + BG_BM - 1) / BG_BM, nt = (N + BG_BN - 1) / BG_BN;
+  int64_t bid = blockIdx.x;
+  const int64_t tn = bid % nt;
+  bid /= nt;
+  const int64_t tm = bid % mt;
+  const int64_t z = bid / mt;
+  const int64_t m0 = tm * BG_BM, n0 = tn * BG_BN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  const int validM = int(M - m0 < BG_BM ? M - m0 : BG_BM);
+  const int validN = int(N - n0 < BG_BN ? N - n0 : BG_BN);
+  for (int i = tid; i < BG_BM; i += 256) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
+  for (int i = tid; i < BG_BN; i += 256) cnT[i] = scatter_bits(n0 + i, a.cn, a.nn);
+  const int64_t czv = scatter_bits(z, a.cz, a.nz);
+  const _Float16* Ab = static_cast<const _Float16*>(a.A) + 2 * ((a.offA ? a.offA[z] : z * M * K) + m0 * K);
+  const _Float16* Bb = static_cast<const _Float16*>(a.B) + 2 * ((a.offB ? a.offB[z] : z * N * K) + n0 * K);
+
+  // one 16 B chunk = 4 complex; a tile row of 32 complex = 8 chunks
+  uint4 ra[8], rb[2];
+  auto fetch = [&](const _Float16* base, int valid, int row, int ch, int64_t k0) -> uint4 {
+    const int64_t kc = k0 + 4 * ch;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (row < valid) {
+      const _Float16* p = base + 2 * (int64_t(row) * K + kc);
+      if (kc + 4 <= K) {
+        v = *reinterpret_cast<const uint4*>(p);
+      } else if (kc < K) {
+        uint32_t t[4] = {0, 0, 0, 0};
+        for (int e = 0; e < 4 && kc + e < K; ++e) t[e] = reinterpret_cast<const uint32_t*>(p)[e];
+        v = make_uint4(t[0], t[1], t[2], t[3]);
+      }
+    }
+    return v;
+  };
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int c = tid + 256 * i;
+      ra[i] = fetch(Ab, validM, c >> 3, c & 7, k0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int c = tid + 256 * i;
+      rb[i] = fetch(Bb, validN, c >> 3, c & 7, k0);
+    }
+  };
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  load(0);
+  for (int64_t k0 = 0; k0 < K; k0 += BG_BK) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int c = tid + 256 * i;
+      *reinterpret_cast<uint4*>(&sA[(c >> 3) * BG_LDK + 8 * (c & 7)]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int c = tid + 256 * i;
+      *reinterpret_cast<uint4*>(&sB[(c >> 3) * BG_LDK + 8 * (c & 7)]) = rb[i];
+    }
+    __syncthreads();
+    if (k0 + BG_BK < K) load(k0 + BG_BK);
+#pragma unroll
+    for (int kk = 0; kk < BG_BK; kk += 8) {
+      const int koff = 2 * (kk + 4 * (lane >> 5));   // halves
+      f16x8 af[4], bf[2];
+#pragma unroll
+      for (int bm = 0; bm < 4; ++bm)
+        af[bm] = *reinterpret_cast<const f16x8*>(&sA[(wm * 128 + bm * 32 + (lane & 31)) * BG_LDK + koff]);
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) {
+        const int np = wn * 64 + bn * 32 + (lane & 31);
+        uint4 raw = *reinterpret_cast<const uint4*>(&sB[(np >> 1) * BG_LDK + koff]);
+        bf[bn] = bprime_frag(raw, np & 1);
+      }
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+        for (int bm = 0; bm < 4; ++bm)
+          acc[bn][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[bn], af[bm], acc[bn][bm], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  TO* C = static_cast<TO*>(a.C);
+  float lmax = 0.0f;
+  unsigned lsat = 0;
+#pragma unroll
+  for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+    for (int bm = 0; bm < 4; ++bm) {
+      const int ml = wm * 128 + bm * 32 + (lane & 31);
+      if (ml >= validM) continue;
+      const int64_t cb = czv + cmT[ml];
+#pragma unroll
+      for (int v = 0; v < 16; v += 2) {
+        const int np = wn * 64 + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int nl = np >> 1;
+        if (nl >= validN) continue;
+        const float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
+        lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+        if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
+      }
+    }
+  block_amax_sat(lmax, lsat, a.amax, a.sat);
+}
+
 // ------------------------------------------------------------ launchers
 bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
-  (void)in_dt;
   (void)nz;
   (void)nk;
   if (kernel == K_THIN) return true;
   if (kernel == K_MFMA) return nm >= 5 && nn >= 4;
+  if (kernel == K_MFMA_BIG) return in_dt == 1 && nm >= 7 && nn >= 5;
   return false;
+}
+
+template <typename TA, typename TB, typename TO>
+static hipError_t launch_thin(const GettArgs& a, hipStream_t s) {
+  const int64_t rows = (int64_t(1) << a.nz) << a.nm;
+  int64_t blocks = (rows + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL((gett_thin<TA, TB, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 template <typename TI, typename TO>
 static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
-  if (kernel == K_THIN) {
-    const int64_t rows = (int64_t(1) << a.nz) << a.nm;
-    int64_t blocks = (rows + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL((gett_thin<TI, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
-  } else {
-    const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn;
+  if (kernel == K_THIN) return launch_thin<TI, TI, TO>(a, s);
+  const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn;
+  if (kernel == K_MFMA) {
     const int64_t blocks = (int64_t(1) << a.nz) * ((M + MF_BM - 1) / MF_BM) * ((N + MF_BN - 1) / MF_BN);
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((gett_mfma<TI, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+  } else {
+    if constexpr (std::is_same<TI, _Float16>::value) {
+      const int64_t blocks = (int64_t(1) << a.nz) * ((M + BG_BM - 1) / BG_BM) * ((N + BG_BN - 1) / BG_BN);
+      if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((gett_mfma_big<TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_gett(int kernel, int in_dt, int out_dt, const GettArgs& a, hipStream_t s) {
+hipError_t launch_gett(int kernel, int a_dt, int b_dt, int out_dt, const GettArgs& a, hipStream_t s) {
+  if (a_dt != b_dt) {
+    // mixed operands: complex-half A with a complex64 B, streaming kernel only
+    if (a_dt != 1 || b_dt != 0) return hipErrorInvalidValue;
+    return out_dt ? launch_thin<_Float16, float, _Float16>(a, s) : launch_thin<_Float16, float, float>(a, s);
+  }
+  const int in_dt = a_dt;
   if (!kernel_applicable(kernel, in_dt, a.nz, a.nm, a.nn, a.nk)) kernel = K_THIN;
   if (in_dt == 0 && out_dt == 0) return launch_typed<float, float>(kernel, a, s);
   if (in_dt == 0 && out_dt == 1) return launch_typed<float, _Float16>(kernel, a, s);
@@ -427,6 +589,15 @@ __device__ __forceinline__ bool topk_better(double p, int64_t j, double q, int64
   return p > q || (p == q && j < i);
 }
 
+// p = re*re + im*im with each product and the sum rounded separately (the
+// compiler must not fuse them into a multiply-add)
+__device__ __forceinline__ double prob_of(double re, double im) {
+#pragma clang fp contract(off)
+  const double rr = re * re;
+  const double ii = im * im;
+  return rr + ii;
+}
+
 __global__ void __launch_bounds__(256) topk_kernel(const double* amps, int64_t group_size, int k,
                                                    int64_t* out_idx, double* out_prob) {
   __shared__ double sp[4];
@@ -441,7 +612,7 @@ __global__ void __launch_bounds__(256) topk_kernel(const double* amps, int64_t g
     int64_t bj = INT64_MAX;
     for (int64_t j = threadIdx.x; j < group_size; j += blockDim.x) {
       const double re = base[2 * j], im = base[2 * j + 1];
-      const double p = __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+      const double p = prob_of(re, im);
       const bool after = !have_prev || p < prev_p || (p == prev_p && j > prev_j);
       if (after && topk_better(p, j, bp, bj)) { bp = p; bj = j; }
     }

@@ -115,6 +115,7 @@ struct PlanOptions {
   uint64_t seed = 1;
   int cost_model = COST_FLOPMEM;
   int dtype = 0;               // 0 complex64, 1 complex-half
+  int search_dtype = 0;        // arithmetic whose step costs the search minimises
   int chalf_min_log2 = 16;     // tensors at least this large run in half
   double bytes_per_elem = 8.0;
 };
@@ -146,6 +147,8 @@ struct StepLayout {
   std::vector<int64_t> cz, cm, cn;   // C element stride of each bit (bit 0 = lowest)
   bool variant = true;               // depends on the slice
   int dtype = 0;                     // compute type: 0 c64, 1 chalf
+  int b_dtype = 0;                   // storage type of operand B (differs only for
+                                     // a small B kept in complex64 beside a half A)
   int out_dtype = 0;
   double macs = 0, bytes = 0;
   int kernel = 0;                    // chosen variant (autotuner)

@@ -586,7 +586,7 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
     c.order = forced_order;
     c.tree = t;
     evaluate_sets(C, leaf_idx, c.tree, c.e);
-    Score s = score(C, c.tree, c.e, c.sl, int(c.order.size()), cf, opt.dtype, opt.chalf_min_log2);
+    Score s = score(C, c.tree, c.e, c.sl, int(c.order.size()), cf, opt.search_dtype, opt.chalf_min_log2);
     // over the cap only counts when the slices are fixed by the caller
     c.key = s.total + (fixed_slices && s.max_w > cap ? 1e30 * (s.max_w - cap) : 0);
     if (c.key < best.key) best = std::move(c);
@@ -627,12 +627,12 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
   // 2. anneal the best tree (half of the budget), with the forced slices
   const long sa_half = std::max(0L, opt.sa_iters / 2);
   auto current = [&]() {
-    return score(C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.dtype,
+    return score(C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.search_dtype,
                  opt.chalf_min_log2);
   };
   if (sa_half > 0) {
     int lim = fixed_slices ? std::max(cap, current().max_w) : INT_MAX / 4;
-    Annealer an{C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.dtype,
+    Annealer an{C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.search_dtype,
                 opt.chalf_min_log2, lim};
     an.run(sa_half, opt.seed + 101, 0.05, 0.002);
     evaluate_sets(C, leaf_idx, best.tree, best.e);
@@ -646,11 +646,11 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
     for (Score sc = current(); sc.max_w > cap; sc = current(), ++rounds) {
       if (int(best.order.size()) >= 62) return "no tree fits the memory cap within 62 sliced wires";
       int target = std::max(cap, sc.max_w - per_round);
-      greedy_slice(C, best.tree, best.e, target, cf, opt.dtype, opt.chalf_min_log2, best.sl,
+      greedy_slice(C, best.tree, best.e, target, cf, opt.search_dtype, opt.chalf_min_log2, best.sl,
                    best.order, std::min(per_round, 62 - int(best.order.size())));
       if (sa_half > 0) {
         int lim = std::max(cap, current().max_w);
-        Annealer an{C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.dtype,
+        Annealer an{C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.search_dtype,
                     opt.chalf_min_log2, lim};
         an.run(std::max(1L, sa_half / 16), opt.seed + 7 * rounds, 0.03, 0.002);
         evaluate_sets(C, leaf_idx, best.tree, best.e);
@@ -664,7 +664,7 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
       for (size_t i = 0; i < best.order.size(); ++i) {
         Bits s2 = best.sl;
         s2.reset(best.order[i]);
-        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) - 1, cf, opt.dtype,
+        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) - 1, cf, opt.search_dtype,
                          opt.chalf_min_log2);
         if (sc.max_w <= cap && sc.total < cur.total) {
           best.sl = s2;
@@ -686,7 +686,7 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
       cand.each([&](int x) {
         Bits s2 = best.sl;
         s2.set(x);
-        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) + 1, cf, opt.dtype,
+        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) + 1, cf, opt.search_dtype,
                          opt.chalf_min_log2);
         if (sc.total < bv) { bv = sc.total; bx = x; }
       });
@@ -695,7 +695,7 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
       best.order.push_back(bx);
     }
   }
-  Score fin = score(C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.dtype,
+  Score fin = score(C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.search_dtype,
                     opt.chalf_min_log2);
   if (fin.max_w > cap) return "no tree fits the memory cap with the slices allowed";
 
@@ -796,17 +796,27 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
     s.macs = std::ldexp(1.0, s.nz + s.nm + s.nn + s.nk);
     rev.push_back(s);
   }
+  // A complex-half step whose B side is a narrow tensor (a gate or a small
+  // branch: nn + nk <= 6 bits) keeps B in complex64: it runs on the
+  // streaming kernel, which reads B once per row from cache, so B costs no
+  // HBM traffic and is never rounded to half.
+  for (auto& s : rev) {
+    s.b_dtype = s.dtype;
+    if (s.dtype == 1 && s.nn + s.nk <= 6) s.b_dtype = 0;
+  }
   hp.steps.assign(rev.rbegin(), rev.rend());
   hp.step_of_node.assign(N, -1);
   for (size_t i = 0; i < hp.steps.size(); ++i) hp.step_of_node[hp.steps[i].out] = int(i);
   for (auto& s : hp.steps) {
     int par = T.parent[s.out];
-    s.out_dtype = par < 0 ? s.dtype : hp.steps[hp.step_of_node[par]].dtype;
+    if (par < 0) { s.out_dtype = s.dtype; continue; }
+    const StepLayout& c = hp.steps[hp.step_of_node[par]];
+    s.out_dtype = s.out == c.b ? c.b_dtype : c.dtype;
   }
   for (auto& s : hp.steps) {
     auto es = [&](int node) {
-      int par = T.parent[node];
-      return hp.steps[hp.step_of_node[par]].dtype ? 4.0 : 8.0;
+      const StepLayout& c = hp.steps[hp.step_of_node[T.parent[node]]];
+      return (node == c.b ? c.b_dtype : c.dtype) ? 4.0 : 8.0;
     };
     s.bytes = es(s.a) * std::ldexp(1.0, s.nz + s.nm + s.nk) +
               es(s.b) * std::ldexp(1.0, s.nz + s.nn + s.nk) +

@@ -24,8 +24,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <array>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -34,7 +36,9 @@
 #include "plan.h"
 
 namespace lf {
-const CostFn* mlp_cost_fn();  // costmodel.cpp (nullptr when no model is loaded)
+// costmodel.hip: the loaded learned cost, tabulated for batch exponent nb
+// (nullptr when no model is loaded or its evaluation failed)
+const CostFn* mlp_cost_fn_for(int nb, std::string* err);
 }
 
 namespace {
@@ -78,6 +82,7 @@ struct lf_plan {
   bool bound = false;
   bool invariant_done = false;
   bool calibrated = false;
+  bool tuned = false;
   // graph cache
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -123,9 +128,12 @@ std::string plan_memory(lf_plan* P) {
     for (int x : hp.order[n]) if (!is_sliced[x]) w += bits_of[x];
     P->elems[n] = int64_t(1) << w;
     int par = hp.tree.parent[n];
-    if (par >= 0) P->store_dt[n] = hp.steps[hp.step_of_node[par]].dtype;
-    else if (n >= L) P->store_dt[n] = hp.steps[hp.step_of_node[n]].out_dtype;
-    else P->store_dt[n] = 0;
+    if (par >= 0) {
+      const StepLayout& c = hp.steps[hp.step_of_node[par]];
+      P->store_dt[n] = n == c.b ? c.b_dtype : c.dtype;
+    } else {
+      P->store_dt[n] = n >= L ? hp.steps[hp.step_of_node[n]].out_dtype : 0;
+    }
   }
   auto bytes_of = [&](int n) { return P->elems[n] * (P->store_dt[n] ? 4 : 8); };
 
@@ -262,6 +270,18 @@ void leaf_layout(const lf_plan* P, int i, std::vector<cd>& out) {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+// Shape rule used until the autotuner has measured a shape.
+int default_kernel(int dtype, int nz, int nm, int nn, int nk) {
+  if (dtype == 1 && nk >= 3 && kernel_applicable(K_MFMA_BIG, dtype, nz, nm, nn, nk)) return K_MFMA_BIG;
+  if (nk >= 2 && kernel_applicable(K_MFMA, dtype, nz, nm, nn, nk)) return K_MFMA;
+  return K_THIN;
+}
+
+// Autotuner results shared by all plans of the process: fastest kernel per
+// (nz, nm, nn, nk, compute type, result type).
+std::mutex g_tune_mu;
+std::map<std::array<int, 6>, int> g_tune;
+
 GettArgs step_args(const lf_plan* P, int s) {
   const StepLayout& st = P->hp.steps[s];
   GettArgs a{};
@@ -291,7 +311,7 @@ GettArgs step_args(const lf_plan* P, int s) {
 lf_status run_step(lf_plan* P, int s, hipStream_t stream) {
   const StepLayout& st = P->hp.steps[s];
   GettArgs a = step_args(P, s);
-  hipError_t e = launch_gett(st.kernel, st.dtype, P->store_dt[st.out], a, stream);
+  hipError_t e = launch_gett(st.kernel, P->store_dt[st.a], P->store_dt[st.b], P->store_dt[st.out], a, stream);
   if (e != hipSuccess) return fail(LF_HIP_ERROR, std::string("contraction launch: ") + hipGetErrorString(e));
   return LF_OK;
 }
@@ -319,7 +339,7 @@ lf_status calibrate(lf_plan* P, int64_t sigma, hipStream_t stream) {
       a.scale = 1.0f;
       a.amax_only = 1;
       HIPCHK(launch_zero_u32(reinterpret_cast<unsigned*>(amax_dev + s), 1, stream));
-      HIPCHK(launch_gett(st.kernel, st.dtype, 1, a, stream));
+      HIPCHK(launch_gett(st.kernel, P->store_dt[st.a], P->store_dt[st.b], 1, a, stream));
       float mx = 0;
       HIPCHK(hipMemcpyAsync(&mx, amax_dev + s, sizeof(float), hipMemcpyDeviceToHost, stream));
       HIPCHK(hipStreamSynchronize(stream));
@@ -376,6 +396,8 @@ void lf_plan_opts_default(lf_plan_opts* o) {
   o->launch_mode = LF_LAUNCH_STREAM;
   o->check_overflow = 1;
   o->slices_per_graph = 8;
+  o->search_dtype = -1;
+  o->autotune = 1;
 }
 
 const char* lf_last_error(void) { return g_err.c_str(); }
@@ -395,6 +417,7 @@ lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits
     lf_plan_opts_default(&o);
     if (opts) o = *opts;
     if (o.dtype != LF_C64 && o.dtype != LF_CHALF) return fail(LF_INVALID_ARGUMENT, "dtype");
+    if (o.search_dtype < -1 || o.search_dtype > LF_CHALF) return fail(LF_INVALID_ARGUMENT, "search_dtype");
     if (o.max_log2_intermediate < 1 || o.max_log2_intermediate > 34)
       return fail(LF_INVALID_ARGUMENT, "max_log2_intermediate must be in [1, 34]");
     if (o.launch_mode != LF_LAUNCH_STREAM && o.launch_mode != LF_LAUNCH_GRAPH)
@@ -428,6 +451,7 @@ lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits
     po.seed = o.seed;
     po.cost_model = o.cost_model;
     po.dtype = o.dtype;
+    po.search_dtype = o.search_dtype < 0 ? o.dtype : o.search_dtype;
     po.chalf_min_log2 = o.chalf_min_log2;
     if (o.n_forced > 0) {
       if (!o.sliced_wires) return fail(LF_INVALID_ARGUMENT, "sliced_wires is NULL");
@@ -439,8 +463,12 @@ lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits
     }
     const lf::CostFn* cf = nullptr;
     if (o.cost_model == LF_COST_MLP) {
-      cf = lf::mlp_cost_fn();
-      if (!cf) return fail(LF_INVALID_ARGUMENT, "cost_model MLP requested but no model is loaded");
+      std::string e2;
+      cf = lf::mlp_cost_fn_for(P->net.nb, &e2);
+      if (!cf) {
+        if (!e2.empty()) return fail(LF_HIP_ERROR, e2);
+        return fail(LF_INVALID_ARGUMENT, "cost_model MLP requested but no model is loaded");
+      }
     }
     err = lf::plan_network(P->net, po, P->hp, cf);
     if (!err.empty()) {
@@ -450,8 +478,7 @@ lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits
     if (int(P->hp.sliced.size()) > 62) return fail(LF_PLAN_INFEASIBLE, "too many sliced wires");
     // default kernel choice
     for (auto& s : P->hp.steps)
-      s.kernel = lf::kernel_applicable(lf::K_MFMA, s.dtype, s.nz, s.nm, s.nn, s.nk) && s.nk >= 2
-                     ? lf::K_MFMA : lf::K_THIN;
+      s.kernel = s.b_dtype != s.dtype ? lf::K_THIN : default_kernel(s.dtype, s.nz, s.nm, s.nn, s.nk);
     for (auto& s : P->hp.steps)
       if (s.nz > lf::MAXZ || s.nm > lf::MAXMN || s.nn > lf::MAXMN)
         return fail(LF_PLAN_INFEASIBLE, "step rank exceeds kernel limits");
@@ -611,10 +638,72 @@ lf_status lf_plan_bind_workspace(lf_plan* P, void* dev_ptr, uint64_t bytes, void
   return LF_OK;
 }
 
+// Times every applicable kernel on each step of slice `sigma` (in step
+// order, so every step reads real operands), keeps the fastest and leaves
+// all results computed.
+static lf_status autotune(lf_plan* P, int64_t sigma, hipStream_t st) {
+  HIPCHK(launch_instantiate(reinterpret_cast<const SliceCopy*>(P->ws + P->off_copies_tab),
+                            int(P->copies.size()), P->copy_max_n, P->ws, nullptr, sigma, st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  lf_status r = LF_OK;
+  for (size_t s = 0; s < P->hp.steps.size() && r == LF_OK; ++s) {
+    StepLayout& stp = P->hp.steps[s];
+    std::array<int, 6> key{stp.nz, stp.nm, stp.nn, stp.nk, stp.dtype, P->store_dt[stp.out]};
+    int known = -1;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) known = it->second;
+    }
+    if (P->store_dt[stp.a] != P->store_dt[stp.b]) known = K_THIN;  // mixed operands
+    if (known < 0) {
+      float best = 1e30f;
+      int bestk = stp.kernel;
+      bool any_tile = false;
+      for (int k = 1; k < K_COUNT; ++k)
+        any_tile |= kernel_applicable(k, stp.dtype, stp.nz, stp.nm, stp.nn, stp.nk);
+      for (int k = 0; k < K_COUNT && r == LF_OK; ++k) {
+        if (!kernel_applicable(k, stp.dtype, stp.nz, stp.nm, stp.nn, stp.nk)) continue;
+        // the streaming kernel is a candidate only for a narrow side
+        if (k == K_THIN && any_tile && stp.nn + stp.nk > 10) continue;
+        stp.kernel = k;
+        r = run_step(P, int(s), st);  // warm-up
+        if (r) break;
+        const int reps = stp.macs > 1e10 ? 2 : 5;
+        if (hipEventRecord(e0, st) != hipSuccess) { r = fail(LF_HIP_ERROR, "event"); break; }
+        for (int i = 0; i < reps && r == LF_OK; ++i) r = run_step(P, int(s), st);
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          r = fail(LF_HIP_ERROR, "event");
+          break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; bestk = k; }
+      }
+      known = bestk;
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = known;
+    }
+    stp.kernel = known;
+    if (r == LF_OK) r = run_step(P, int(s), st);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r == LF_OK) P->tuned = true;
+  return r;
+}
+
 static lf_status ensure_ready(lf_plan* P, int64_t sigma, hipStream_t st) {
   if (!P->calibrated) {
     lf_status r = calibrate(P, sigma, st);
     if (r) return r;
+  }
+  if (P->opts.autotune && !P->tuned) {
+    lf_status r = autotune(P, sigma, st);
+    if (r) return r;
+    P->invariant_done = true;
   }
   if (!P->invariant_done) {
     for (int s : P->invariant_steps) {
@@ -763,7 +852,7 @@ lf_status lf_contract_pair(int32_t dtype_in, int32_t dtype_out, int32_t kernel, 
   a.scale = scale;
   if (kernel < 0)
     kernel = lf::kernel_applicable(lf::K_MFMA, dtype_in, nz, nm, nn, nk) && nk >= 2 ? lf::K_MFMA : lf::K_THIN;
-  HIPCHK(lf::launch_gett(kernel, dtype_in, dtype_out, a, as_stream(stream)));
+  HIPCHK(lf::launch_gett(kernel, dtype_in, dtype_in, dtype_out, a, as_stream(stream)));
   return LF_OK;
 }
 

@@ -84,7 +84,8 @@ def _scatter(ref, nz, nm, nn, strides):
 SHAPES = [
     # nz, nm, nn, nk: thin, tails below a tile, multi-tile, batch, K = 1
     (0, 10, 2, 2), (0, 3, 1, 0), (2, 6, 5, 3), (0, 8, 7, 6), (3, 7, 6, 5),
-    (0, 9, 6, 9), (1, 4, 4, 1), (0, 5, 4, 4), (0, 12, 8, 4),
+    (0, 9, 6, 9), (1, 4, 4, 1), (0, 5, 4, 4), (0, 12, 8, 4), (0, 8, 6, 1), (2, 7, 5, 0),
+    (0, 9, 7, 2),
 ]
 
 
@@ -112,12 +113,14 @@ def _to_half_pairs(x, e):
     return torch.from_numpy(v.astype(np.float16)).cuda()
 
 
-@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("kernel", [0, 1, 2])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_pair_chalf(lf, kernel, shape):
     nz, nm, nn, nk = shape
     if kernel == 1 and not (nm >= 5 and nn >= 4):
         pytest.skip("MFMA tile needs nm >= 5 and nn >= 4")
+    if kernel == 2 and not (nm >= 7 and nn >= 5):
+        pytest.skip("large MFMA tile needs nm >= 7 and nn >= 5")
     _say(f"pair chalf kernel={kernel} shape={shape}")
     A = wl.random_complex((1 << (nz + nm + nk),), seed=11 + sum(shape))
     B = wl.random_complex((1 << (nz + nn + nk),), seed=12 + sum(shape))
