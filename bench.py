@@ -21,9 +21,35 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MI355X = {"hbm_gbs": 8000.0, "fp16_tflops": 2500.0, "fp32_tflops": 157.3}
-KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big"}
+# kernel ids of the contraction steps; the two large tiles are one template
+# (gett_mfma_big<TO, WM, WN, MINB>) with 4x2 and 4x4 wave layouts
+KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big<4,2,2>", 3: "gett_narrow",
+                4: "gett_mfma_big<4,4,1>"}
 # planner settings per workload (search effort, not inputs)
 PLAN_OPTS = {"rqc53": {"sa_iters": 4_000_000}}
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "runtime.hip"):
+        with open(os.path.join(ROOT, "paper_2406_18889_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload, dtype, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken with the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{dtype}.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch", {}).get(kernel)
 
 
 def parse():
@@ -39,6 +65,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--dump-steps", default="", help="write per-step shapes and times (json)")
+    ap.add_argument("--autotune-cache", default="", help="load/save the kernel choices here")
+    ap.add_argument("--trace", action="store_true",
+                    help="timed steps only (for an external profiler): no per-step timing, "
+                         "no second arithmetic, no CPU baseline")
     return ap.parse_args()
 
 
@@ -103,6 +133,8 @@ def main():
     import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.autotune_cache and os.path.exists(args.autotune_cache):
+        lf.autotune_load(args.autotune_cache)
     circ, openq, cb, spec = wl.standard_workload(args.workload)
     kw = dict(PLAN_OPTS.get(args.workload, {}))
     if args.workload == "rqc30":
@@ -141,29 +173,42 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = done / dt
+    if args.autotune_cache:
+        lf.autotune_save(args.autotune_cache)
+    if args.trace:
+        print(json.dumps({"trace": True, "value": value, "unit": "slices/s", "steps": args.steps,
+                          "slices_per_step": S, "workload": args.workload, "dtype": args.dtype,
+                          "source_hash": source_hash()}))
+        return
 
-    # per-step kernel timing (HIP events on the plan's stream) -> dominant step
+    # per-step kernel timing (HIP events on the plan's stream); the dominant
+    # kernel is the variant with the largest total time per slice, reported
+    # over all of its launches in a slice (as a per-kernel profiler does)
     ms = plan.profile_steps(reps=3)
     dims, macs, byts = plan.steps()
     var = dims[:, 4] == 1
-    share = np.where(var, ms, 0.0)
-    dom = int(np.argmax(share))
-    flops = 8.0 * macs[dom]
-    ai = flops / byts[dom]
-    half = dims[dom, 5] == 1
+    kinds = sorted(set(int(k) for k in dims[var, 7]))
+    tot = {k: float(ms[var & (dims[:, 7] == k)].sum()) for k in kinds}
+    dom_k = max(tot, key=tot.get)
+    sel = var & (dims[:, 7] == dom_k)
+    t = float(ms[sel].sum()) * 1e-3
+    flops = 8.0 * float(macs[sel].sum())
+    bytes_ = float(byts[sel].sum())
+    half = bool((dims[sel, 5] == 1).all())
     peak_tf = MI355X["fp16_tflops"] if half else MI355X["fp32_tflops"]
     ridge = peak_tf * 1e12 / (MI355X["hbm_gbs"] * 1e9)
-    t = ms[dom] * 1e-3
-    if ai >= ridge:
+    if flops / bytes_ >= ridge:
         roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": peak_tf, "unit": "TFLOP/s"}
     else:
-        roof = {"bound": "hbm", "achieved": byts[dom] / t / 1e9, "peak": MI355X["hbm_gbs"], "unit": "GB/s"}
+        roof = {"bound": "hbm", "achieved": bytes_ / t / 1e9, "peak": MI355X["hbm_gbs"], "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = {"step": dom, "nz_nm_nn_nk": [int(x) for x in dims[dom, :4]],
-                      "kind": KERNEL_NAMES.get(int(dims[dom, 7]), "?"),
-                      "ms": float(ms[dom]), "share_of_slice": float(share[dom] / share.sum())}
-
+    roof["traffic"] = traffic_for(args.workload, args.dtype, KERNEL_NAMES.get(dom_k, "?"))
+    roof["kernel"] = {"name": KERNEL_NAMES.get(dom_k, "?"), "launches_per_slice": int(sel.sum()),
+                      "avg_launch_ms": float(ms[sel].mean()),
+                      "algorithmic_flop_per_launch": flops / int(sel.sum()),
+                      "algorithmic_bytes_per_launch": bytes_ / int(sel.sum()),
+                      "share_of_slice": tot[dom_k] / sum(tot.values())}
+    roof["by_kernel_ms_per_slice"] = {KERNEL_NAMES.get(k, "?"): v for k, v in tot.items()}
     if args.dump_steps:
         with open(args.dump_steps, "w") as f:
             json.dump({"dims": dims.tolist(), "macs": macs.tolist(), "bytes": byts.tolist(),

@@ -162,6 +162,10 @@ lf_status lf_plan_tree(const lf_plan* plan, int32_t* leaf_canon, int32_t* left, 
  */
 lf_status lf_plan_steps(const lf_plan* plan, int32_t* dims, double* macs, double* bytes);
 
+/* Result strides of step s (elements): out[0..nz) for the bits of z, then
+ * nm for m, then nn for n, as in lf_contract_pair; out must hold nz+nm+nn. */
+lf_status lf_plan_step_strides(const lf_plan* plan, int32_t step, int64_t* out);
+
 /*
  * Binds `bytes` of device memory at `dev_ptr` (256-byte aligned, owned by
  * the caller, at least info.workspace_bytes) and uploads the leaf tensors on
@@ -183,6 +187,30 @@ lf_status lf_plan_bind_workspace(lf_plan* plan, void* dev_ptr, uint64_t bytes, v
  */
 lf_status lf_contract_slices(lf_plan* plan, int64_t slice_begin, int64_t slice_end,
                              void* out_amps, void* stream);
+
+/*
+ * Batched execution of many sliced subtasks of uneven shape.  Item i adds
+ * slices [slice_begin, slice_end) of items[i].plan into items[i].out_amps,
+ * exactly as lf_contract_slices would.  Items of the same plan run in item
+ * order (they share that plan's workspace); items of different plans are
+ * independent.  mode LF_BATCH_SEQUENTIAL launches every item's kernels on
+ * `stream` in item order; LF_BATCH_GRAPH records all items once as one
+ * HIP graph, each plan's items a chain and the chains spread over `lanes`
+ * parallel branches (1..8; 0 = pick the fastest of 1, 2 and 4 on the first
+ * call, timed on temporary accumulators the library allocates and frees,
+ * and remember it for this set of plans), and launches it with one
+ * hipGraphLaunch on `stream`; the recorded graph is reused while the items
+ * are unchanged.  Every plan must be bound.  Results are bit-identical
+ * between the modes.  Asynchronous.  Errors: as lf_contract_slices.
+ */
+typedef struct lf_batch_item {
+  lf_plan* plan;
+  int64_t slice_begin, slice_end;
+  void* out_amps;
+} lf_batch_item;
+enum { LF_BATCH_SEQUENTIAL = 0, LF_BATCH_GRAPH = 1 };
+lf_status lf_contract_batch(const lf_batch_item* items, int32_t n_items, int32_t mode,
+                            int32_t lanes, void* stream);
 
 /*
  * Top-k post-selection (Methods A): for each of n_groups consecutive groups
@@ -271,6 +299,12 @@ lf_status lf_costmodel_clear(void);
  * use of nz).  Errors: LF_INVALID_ARGUMENT when no model is loaded. */
 lf_status lf_costmodel_predict(int32_t nz, int32_t nm, int32_t nn, int32_t nk, int32_t dtype,
                                double* seconds);
+
+/* The autotuner's choices (step shape and operand types -> kernel variant)
+ * are shared by all plans of the process; these save them to a text file
+ * and merge them back, so a later process skips the timing runs. */
+lf_status lf_autotune_save(const char* path);
+lf_status lf_autotune_load(const char* path);
 
 void lf_plan_destroy(lf_plan* plan);
 

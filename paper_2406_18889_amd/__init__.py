@@ -3,4 +3,5 @@ post-selection (arXiv 2406.18889) on MI355X: a C-ABI HIP library
 (include/leapfrog.h) with a thin Python binding.
 """
 
-from .api import Plan, build_network, contract_pair, contract_slices, postselect_topk  # noqa: F401
+from .api import (Plan, build_network, contract_batch, contract_pair,  # noqa: F401
+                  contract_slices, postselect_topk)

@@ -52,6 +52,15 @@ class lf_plan_opts(ctypes.Structure):
                 ("autotune", ctypes.c_int32)]
 
 
+class lf_batch_item(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("slice_begin", ctypes.c_int64),
+                ("slice_end", ctypes.c_int64), ("out_amps", ctypes.c_void_p)]
+
+
+LF_BATCH_SEQUENTIAL = 0
+LF_BATCH_GRAPH = 1
+
+
 class lf_plan_info(ctypes.Structure):
     _fields_ = [("n_slices", ctypes.c_int64), ("n_sliced_wires", ctypes.c_int32),
                 ("n_steps", ctypes.c_int32), ("n_variant_steps", ctypes.c_int32),
@@ -78,8 +87,11 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "lf_plan_steps": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "lf_plan_step_strides": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "lf_plan_bind_workspace": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P]),
     "lf_contract_slices": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
+    "lf_contract_batch": (ctypes.c_int32, [ctypes.POINTER(lf_batch_item), ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, _P]),
     "lf_postselect_topk": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P, _P, _P]),
     "lf_profile_steps": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _P]),
     "lf_contract_pair": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P,
@@ -100,6 +112,8 @@ SIGNATURES = {
                                            ctypes.c_float, ctypes.c_float]),
     "lf_costmodel_clear": (ctypes.c_int32, []),
     "lf_costmodel_predict": (ctypes.c_int32, [ctypes.c_int32] * 5 + [ctypes.POINTER(ctypes.c_double)]),
+    "lf_autotune_save": (ctypes.c_int32, [ctypes.c_char_p]),
+    "lf_autotune_load": (ctypes.c_int32, [ctypes.c_char_p]),
     "lf_plan_destroy": (None, [_P]),
     "lf_last_error": (ctypes.c_char_p, []),
 }

@@ -128,6 +128,15 @@ class Plan:
               "lf_plan_steps")
         return dims[:S], macs[:S], byts[:S]
 
+    def step_strides(self, step: int) -> np.ndarray:
+        dims, _, _ = self.steps()
+        n = int(dims[step, 0] + dims[step, 1] + dims[step, 2])
+        out = np.zeros(max(1, n), np.int64)
+        check(self._lib.lf_plan_step_strides(self._handle, step,
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+              "lf_plan_step_strides")
+        return out[:n]
+
     # ------------------------------------------------------------- device
     def bind(self, workspace=None, stream=None):
         """Binds (allocating with torch if not given) the device workspace."""
@@ -189,6 +198,19 @@ def contract_slices(plan: Plan, begin: int, end: int, out_amps=None, stream=None
     return plan.contract(begin, end, out_amps, stream)
 
 
+def contract_batch(items, mode: str = "graph", lanes: int = 0, stream=None):
+    """items: sequence of (plan, slice_begin, slice_end, out_amps tensor)."""
+    arr = (_lib.lf_batch_item * max(1, len(items)))()
+    for i, (plan, s0, s1, out) in enumerate(items):
+        arr[i].plan = plan._handle.value
+        arr[i].slice_begin = int(s0)
+        arr[i].slice_end = int(s1)
+        arr[i].out_amps = out.data_ptr()
+    m = {"sequential": _lib.LF_BATCH_SEQUENTIAL, "graph": _lib.LF_BATCH_GRAPH}[mode]
+    check(_lib.load().lf_contract_batch(arr, len(items), m, lanes, _stream_ptr(stream)),
+          "lf_contract_batch")
+
+
 def postselect_topk(amps, group_size: int, k: int, stream=None):
     """Top-k per group of `group_size` consecutive amplitudes (device tensors)."""
     import torch
@@ -232,3 +254,11 @@ def contract_pair(A, B, C, nz: int, nm: int, nn: int, nk: int, c_strides, scale:
                                        st.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                        float(scale), _stream_ptr(stream)), "lf_contract_pair")
     return C
+
+
+def autotune_save(path: str) -> None:
+    check(_lib.load().lf_autotune_save(path.encode()), "lf_autotune_save")
+
+
+def autotune_load(path: str) -> None:
+    check(_lib.load().lf_autotune_load(path.encode()), "lf_autotune_load")

@@ -38,9 +38,15 @@ struct GettArgs {
   int64_t cn[MAXMN];
 };
 
-// K_THIN: streaming, one row per thread; K_MFMA: 128 x 64 complex tile (both
-// arithmetics); K_MFMA_BIG: 256 x 64 complex tile, complex-half only.
-enum KernelId : int { K_THIN = 0, K_MFMA = 1, K_MFMA_BIG = 2, K_COUNT = 3 };
+// K_THIN: streaming, one row per thread, any shape; K_MFMA: 128 x 64 complex
+// tile (both arithmetics); K_MFMA_BIG: 256 x 64 complex tile, complex-half
+// only; K_NARROW: one row per thread with B staged in LDS, for N K <= 256
+// and M >= 256; K_MFMA_WIDE: 256 x 128 complex tile, complex-half only;
+// K_MFMA_DB: the 256 x 128 tile with double-buffered LDS and an XCD-aware
+// tile order, complex-half only.
+enum KernelId : int {
+  K_THIN = 0, K_MFMA = 1, K_MFMA_BIG = 2, K_NARROW = 3, K_MFMA_WIDE = 4, K_MFMA_DB = 5, K_COUNT = 6
+};
 
 // a_dt, b_dt, out_dt: 0 complex64 (float pairs), 1 complex-half (_Float16
 // pairs).  a_dt != b_dt is allowed only as a complex-half A with a

@@ -68,16 +68,18 @@ template <> struct CIO<_Float16> {
   }
 };
 
+// Saturation count (rare, so an atomic only when nonzero) and, when asked
+// for, the running maximum of |re|,|im| (one atomic per wave).
 __device__ __forceinline__ void block_amax_sat(float local_max, unsigned local_sat, float* amax,
                                                unsigned* sat) {
-  // wave reduction, then one atomic per wave
-  for (int o = 32; o > 0; o >>= 1) {
-    local_max = fmaxf(local_max, __shfl_xor(local_max, o));
-    local_sat += __shfl_xor(local_sat, o);
+  if (sat) {
+    for (int o = 32; o > 0; o >>= 1) local_sat += __shfl_xor(local_sat, o);
+    if ((threadIdx.x & 63) == 0 && local_sat) atomicAdd(sat, local_sat);
   }
-  if ((threadIdx.x & 63) == 0) {
-    if (amax && local_max > 0.0f) atomicMax(reinterpret_cast<unsigned*>(amax), __float_as_uint(local_max));
-    if (sat && local_sat) atomicAdd(sat, local_sat);
+  if (amax) {
+    for (int o = 32; o > 0; o >>= 1) local_max = fmaxf(local_max, __shfl_xor(local_max, o));
+    if ((threadIdx.x & 63) == 0 && local_max > 0.0f)
+      atomicMax(reinterpret_cast<unsigned*>(amax), __float_as_uint(local_max));
   }
 }
 
@@ -136,6 +138,119 @@ __global__ void __launch_bounds__(256) gett_thin(GettArgs a) {
     }
   }
   block_amax_sat(lmax, lsat, a.amax, a.sat);
+}
+
+// ------------------------------------------------------------- narrow
+// Steps whose B side is small (N K <= 256 complex) and M >= 256: every
+// workgroup lies in one batch entry, stages that entry's B in LDS once, and
+// each thread loads its A row (K complex) with vector loads, then forms the
+// N results with B read by broadcast from LDS.  HBM traffic is one read of
+// A and one write of C.
+template <typename T> struct RowLoad;
+template <> struct RowLoad<_Float16> {
+  template <int K>
+  __device__ static __forceinline__ void load(const _Float16* p, float (&re)[K], float (&im)[K]) {
+    if constexpr (K >= 4) {
+#pragma unroll
+      for (int c = 0; c < K / 4; ++c) {
+        uint4 v = reinterpret_cast<const uint4*>(p)[c];
+        uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          f16x2 h;
+          __builtin_memcpy(&h, &w[e], 4);
+          re[4 * c + e] = float(h[0]);
+          im[4 * c + e] = float(h[1]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < K; ++e) {
+        f16x2 h = reinterpret_cast<const f16x2*>(p)[e];
+        re[e] = float(h[0]);
+        im[e] = float(h[1]);
+      }
+    }
+  }
+};
+template <> struct RowLoad<float> {
+  template <int K>
+  __device__ static __forceinline__ void load(const float* p, float (&re)[K], float (&im)[K]) {
+    if constexpr (K >= 2) {
+#pragma unroll
+      for (int c = 0; c < K / 2; ++c) {
+        float4 v = reinterpret_cast<const float4*>(p)[c];
+        re[2 * c] = v.x;
+        im[2 * c] = v.y;
+        re[2 * c + 1] = v.z;
+        im[2 * c + 1] = v.w;
+      }
+    } else {
+      float2 v = reinterpret_cast<const float2*>(p)[0];
+      re[0] = v.x;
+      im[0] = v.y;
+    }
+  }
+};
+
+template <typename TA, typename TB, typename TO, int K>
+__global__ void __launch_bounds__(256) gett_narrow(GettArgs a) {
+  __shared__ float2 sB[256];
+  __shared__ int64_t cnT[256];
+  const int64_t M = int64_t(1) << a.nm;
+  const int N = 1 << a.nn;
+  const int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;  // rows of one z per block
+  const int64_t z = (int64_t(blockIdx.x) * blockDim.x) >> a.nm;
+  const int64_t bz = a.offB ? a.offB[z] : z * N * K;
+  const TB* B = static_cast<const TB*>(a.B);
+  for (int i = threadIdx.x; i < N * K; i += blockDim.x) {
+    float br, bi;
+    CIO<TB>::load(B, bz + i, br, bi);
+    sB[i] = make_float2(br, bi);
+  }
+  for (int i = threadIdx.x; i < N; i += blockDim.x) cnT[i] = scatter_bits(i, a.cn, a.nn);
+  __syncthreads();
+  const int64_t m = r & (M - 1);
+  const int64_t arow = (a.offA ? a.offA[z] : z * M * K) + m * K;
+  float ar[K], ai[K];
+  RowLoad<TA>::template load<K>(static_cast<const TA*>(a.A) + 2 * arow, ar, ai);
+  const int64_t cbase = scatter_bits(z, a.cz, a.nz) + scatter_bits(m, a.cm, a.nm);
+  TO* C = static_cast<TO*>(a.C);
+  float lmax = 0.0f;
+  unsigned lsat = 0;
+  for (int n = 0; n < N; ++n) {
+    float cr = 0.f, ci = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float2 b = sB[n * K + k];
+      cr += ar[k] * b.x - ai[k] * b.y;
+      ci += ar[k] * b.y + ai[k] * b.x;
+    }
+    cr *= a.scale;
+    ci *= a.scale;
+    lmax = fmaxf(lmax, fmaxf(fabsf(cr), fabsf(ci)));
+    if (!a.amax_only) lsat += CIO<TO>::store(C, cbase + cnT[n], cr, ci);
+  }
+  block_amax_sat(lmax, lsat, a.amax, a.sat);
+}
+
+template <typename TA, typename TB, typename TO>
+static hipError_t launch_narrow(const GettArgs& a, hipStream_t s) {
+  const int64_t rows = (int64_t(1) << a.nz) << a.nm;
+  const int64_t blocks = rows / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 g = dim3(unsigned(blocks)), b = dim3(256);
+  switch (a.nk) {
+    case 0: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 1>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 2>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 4>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 8>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 16>), g, b, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 32>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 64>), g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // --------------------------------------------------------------- MFMA
@@ -309,13 +424,14 @@ __global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
 }
 
 // ------------------------------------------------ MFMA, large f16 tile
-// Complex-half operands, block tile 256 (m) x 64 (complex n) x 32 (complex
-// k); waves 2 (m) x 2 (n); each wave owns 4 x 2 MFMA 32x32x16 blocks
-// (128 m x 64 rows of B').  Both LDS tiles hold plain (re, im) rows; the B'
+// Complex-half operands.  Four waves in 2 (m) x 2 (n) arrangement; each wave
+// owns WM x WN MFMA 32x32x16 blocks (32 WM values of m by 32 WN rows of B',
+// i.e. 16 WN complex n), so the block tile is 64 WM (m) x 32 WN (complex n)
+// x 32 (complex k).  Both LDS tiles hold plain (re, im) rows; the B'
 // fragment of a lane is formed in registers from 4 complex values of row
 // n = n'/2: row 2n gets (Br, -Bi), row 2n+1 gets (Bi, Br).  The next K tile
 // is fetched from HBM into registers while the current one is multiplied.
-constexpr int BG_BM = 256, BG_BN = 64, BG_BK = 32;
+constexpr int BG_BK = 32;
 constexpr int BG_LDK = 2 * BG_BK + 8;  // halves per LDS row (16 B pad)
 
 __device__ __forceinline__ f16x8 bprime_frag(uint4 raw, int parity) {
@@ -328,33 +444,40 @@ __device__ __forceinline__ f16x8 bprime_frag(uint4 raw, int parity) {
   return r;
 }
 
-template <typename TO>
-__global__ void __launch_bounds__(256, 2) gett_mfma_big(GettArgs a) {
-  __shared__ __attribute__((aligned(16))) _Float16 sA[BG_BM * BG_LDK];
-  __shared__ __attribute__((aligned(16))) _Float16 sB[BG_BN * BG_LDK];
-  __shared__ int64_t cmT[BG_BM];
-  __shared__ int64_t cnT[BG_BN];
+template <int WM, int WN> struct BigTile {
+  static constexpr int BM = 64 * WM;   // m per block
+  static constexpr int BN = 32 * WN;   // complex n per block
+};
+
+template <typename TO, int WM, int WN, int MINB>
+__global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
+  constexpr int BM = BigTile<WM, WN>::BM, BN = BigTile<WM, WN>::BN;
+  constexpr int NA = BM * 8 / 256, NB = BN * 8 / 256;   // 16 B chunks per thread
+  __shared__ __attribute__((aligned(16))) _Float16 sA[BM * BG_LDK];
+  __shared__ __attribute__((aligned(16))) _Float16 sB[BN * BG_LDK];
+  __shared__ int64_t cmT[BM];
+  __shared__ int64_t cnT[BN];
 
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
-  const int64_t mt = (M + BG_BM - 1) / BG_BM, nt = (N + BG_BN - 1) / BG_BN;
+  const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN;
   int64_t bid = blockIdx.x;
   const int64_t tn = bid % nt;
   bid /= nt;
   const int64_t tm = bid % mt;
   const int64_t z = bid / mt;
-  const int64_t m0 = tm * BG_BM, n0 = tn * BG_BN;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
-  const int validM = int(M - m0 < BG_BM ? M - m0 : BG_BM);
-  const int validN = int(N - n0 < BG_BN ? N - n0 : BG_BN);
-  for (int i = tid; i < BG_BM; i += 256) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
-  for (int i = tid; i < BG_BN; i += 256) cnT[i] = scatter_bits(n0 + i, a.cn, a.nn);
+  const int validM = int(M - m0 < BM ? M - m0 : BM);
+  const int validN = int(N - n0 < BN ? N - n0 : BN);
+  for (int i = tid; i < BM; i += 256) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
+  for (int i = tid; i < BN; i += 256) cnT[i] = scatter_bits(n0 + i, a.cn, a.nn);
   const int64_t czv = scatter_bits(z, a.cz, a.nz);
   const _Float16* Ab = static_cast<const _Float16*>(a.A) + 2 * ((a.offA ? a.offA[z] : z * M * K) + m0 * K);
   const _Float16* Bb = static_cast<const _Float16*>(a.B) + 2 * ((a.offB ? a.offB[z] : z * N * K) + n0 * K);
 
   // one 16 B chunk = 4 complex; a tile row of 32 complex = 8 chunks
-  uint4 ra[8], rb[2];
+  uint4 ra[NA], rb[NB];
   auto fetch = [&](const _Float16* base, int valid, int row, int ch, int64_t k0) -> uint4 {
     const int64_t kc = k0 + 4 * ch;
     uint4 v = make_uint4(0, 0, 0, 0);
@@ -372,34 +495,34 @@ __global__ void __launch_bounds__(256, 2) gett_mfma_big(GettArgs a) {
   };
   auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NA; ++i) {
       const int c = tid + 256 * i;
       ra[i] = fetch(Ab, validM, c >> 3, c & 7, k0);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NB; ++i) {
       const int c = tid + 256 * i;
       rb[i] = fetch(Bb, validN, c >> 3, c & 7, k0);
     }
   };
 
-  f32x16 acc[2][4];
+  f32x16 acc[WN][WM];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WN; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < WM; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
   load(0);
   for (int64_t k0 = 0; k0 < K; k0 += BG_BK) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NA; ++i) {
       const int c = tid + 256 * i;
       *reinterpret_cast<uint4*>(&sA[(c >> 3) * BG_LDK + 8 * (c & 7)]) = ra[i];
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NB; ++i) {
       const int c = tid + 256 * i;
       *reinterpret_cast<uint4*>(&sB[(c >> 3) * BG_LDK + 8 * (c & 7)]) = rb[i];
     }
@@ -408,20 +531,20 @@ __global__ void __launch_bounds__(256, 2) gett_mfma_big(GettArgs a) {
 #pragma unroll
     for (int kk = 0; kk < BG_BK; kk += 8) {
       const int koff = 2 * (kk + 4 * (lane >> 5));   // halves
-      f16x8 af[4], bf[2];
+      f16x8 af[WM], bf[WN];
 #pragma unroll
-      for (int bm = 0; bm < 4; ++bm)
-        af[bm] = *reinterpret_cast<const f16x8*>(&sA[(wm * 128 + bm * 32 + (lane & 31)) * BG_LDK + koff]);
+      for (int bm = 0; bm < WM; ++bm)
+        af[bm] = *reinterpret_cast<const f16x8*>(&sA[(wm * 32 * WM + bm * 32 + (lane & 31)) * BG_LDK + koff]);
 #pragma unroll
-      for (int bn = 0; bn < 2; ++bn) {
-        const int np = wn * 64 + bn * 32 + (lane & 31);
+      for (int bn = 0; bn < WN; ++bn) {
+        const int np = wn * 32 * WN + bn * 32 + (lane & 31);
         uint4 raw = *reinterpret_cast<const uint4*>(&sB[(np >> 1) * BG_LDK + koff]);
         bf[bn] = bprime_frag(raw, np & 1);
       }
 #pragma unroll
-      for (int bn = 0; bn < 2; ++bn)
+      for (int bn = 0; bn < WN; ++bn)
 #pragma unroll
-        for (int bm = 0; bm < 4; ++bm)
+        for (int bm = 0; bm < WM; ++bm)
           acc[bn][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[bn], af[bm], acc[bn][bm], 0, 0, 0);
     }
     __syncthreads();
@@ -431,15 +554,171 @@ __global__ void __launch_bounds__(256, 2) gett_mfma_big(GettArgs a) {
   float lmax = 0.0f;
   unsigned lsat = 0;
 #pragma unroll
-  for (int bn = 0; bn < 2; ++bn)
+  for (int bn = 0; bn < WN; ++bn)
 #pragma unroll
-    for (int bm = 0; bm < 4; ++bm) {
-      const int ml = wm * 128 + bm * 32 + (lane & 31);
+    for (int bm = 0; bm < WM; ++bm) {
+      const int ml = wm * 32 * WM + bm * 32 + (lane & 31);
       if (ml >= validM) continue;
       const int64_t cb = czv + cmT[ml];
 #pragma unroll
       for (int v = 0; v < 16; v += 2) {
-        const int np = wn * 64 + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int np = wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int nl = np >> 1;
+        if (nl >= validN) continue;
+        const float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
+        lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+        if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
+      }
+    }
+  block_amax_sat(lmax, lsat, a.amax, a.sat);
+}
+
+// ------------------------------------ MFMA, pipelined f16 tile (LDS ping-pong)
+// Same operand handling as gett_mfma_big with the 4 x 4 wave layout (block
+// tile 256 m x 128 complex n x 32 complex k), but two LDS buffers: while the
+// MFMAs consume tile t from one buffer, tile t+1 is fetched from HBM into
+// registers and written to the other buffer afterwards, so each K step needs
+// one barrier instead of two and the LDS writes overlap the matrix cores.
+// The block index is remapped so that each of the 8 XCDs (which receive
+// blocks round-robin) works on a contiguous range of tiles, and within it
+// tiles run in groups of DB_GROUP m-tiles that sweep n together, so
+// concurrently resident blocks share A and B panels in their XCD's L2.
+constexpr int DB_WM = 4, DB_WN = 4, DB_GROUP = 8;
+constexpr int DB_BM = 64 * DB_WM, DB_BN = 32 * DB_WN;
+
+__device__ __forceinline__ void db_tile_of(int64_t bid, int64_t nblk, int64_t mt, int64_t nt, int64_t& z,
+                                           int64_t& tm, int64_t& tn) {
+  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  const int64_t per_z = mt * nt;
+  z = bid / per_z;
+  const int64_t r = bid - z * per_z;
+  const int64_t per_group = int64_t(DB_GROUP) * nt;
+  const int64_t g = r / per_group, rg = r - g * per_group;
+  const int64_t first = g * DB_GROUP;
+  const int64_t gsz = mt - first < DB_GROUP ? mt - first : DB_GROUP;
+  tm = first + rg % gsz;
+  tn = rg / gsz;
+}
+
+template <typename TO>
+__global__ void __launch_bounds__(256, 1) gett_mfma_db(GettArgs a) {
+  constexpr int BM = DB_BM, BN = DB_BN;
+  constexpr int NA = BM * 8 / 256, NB = BN * 8 / 256;   // 16 B chunks per thread
+  __shared__ __attribute__((aligned(16))) _Float16 sA[2][BM * BG_LDK];
+  __shared__ __attribute__((aligned(16))) _Float16 sB[2][BN * BG_LDK];
+  __shared__ int64_t cmT[BM];
+  __shared__ int64_t cnT[BN];
+
+  const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
+  const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN;
+  int64_t z, tm, tn;
+  db_tile_of(blockIdx.x, gridDim.x, mt, nt, z, tm, tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  const int validM = int(M - m0 < BM ? M - m0 : BM);
+  const int validN = int(N - n0 < BN ? N - n0 : BN);
+  for (int i = tid; i < BM; i += 256) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
+  for (int i = tid; i < BN; i += 256) cnT[i] = scatter_bits(n0 + i, a.cn, a.nn);
+  const int64_t czv = scatter_bits(z, a.cz, a.nz);
+  const _Float16* Ab = static_cast<const _Float16*>(a.A) + 2 * ((a.offA ? a.offA[z] : z * M * K) + m0 * K);
+  const _Float16* Bb = static_cast<const _Float16*>(a.B) + 2 * ((a.offB ? a.offB[z] : z * N * K) + n0 * K);
+
+  uint4 ra[NA], rb[NB];
+  auto fetch = [&](const _Float16* base, int valid, int row, int ch, int64_t k0) -> uint4 {
+    const int64_t kc = k0 + 4 * ch;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (row < valid) {
+      const _Float16* p = base + 2 * (int64_t(row) * K + kc);
+      if (kc + 4 <= K) {
+        v = *reinterpret_cast<const uint4*>(p);
+      } else if (kc < K) {
+        uint32_t t[4] = {0, 0, 0, 0};
+        for (int e = 0; e < 4 && kc + e < K; ++e) t[e] = reinterpret_cast<const uint32_t*>(p)[e];
+        v = make_uint4(t[0], t[1], t[2], t[3]);
+      }
+    }
+    return v;
+  };
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int c = tid + 256 * i;
+      ra[i] = fetch(Ab, validM, c >> 3, c & 7, k0);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int c = tid + 256 * i;
+      rb[i] = fetch(Bb, validN, c >> 3, c & 7, k0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int c = tid + 256 * i;
+      *reinterpret_cast<uint4*>(&sA[buf][(c >> 3) * BG_LDK + 8 * (c & 7)]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int c = tid + 256 * i;
+      *reinterpret_cast<uint4*>(&sB[buf][(c >> 3) * BG_LDK + 8 * (c & 7)]) = rb[i];
+    }
+  };
+
+  f32x16 acc[DB_WN][DB_WM];
+#pragma unroll
+  for (int i = 0; i < DB_WN; ++i)
+#pragma unroll
+    for (int j = 0; j < DB_WM; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  const int64_t T = (K + BG_BK - 1) / BG_BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int64_t t = 0; t < T; ++t) {
+    const int cur = int(t & 1);
+    if (t + 1 < T) load((t + 1) * BG_BK);
+    const _Float16* cA = sA[cur];
+    const _Float16* cB = sB[cur];
+#pragma unroll
+    for (int kk = 0; kk < BG_BK; kk += 8) {
+      const int koff = 2 * (kk + 4 * (lane >> 5));   // halves
+      f16x8 af[DB_WM], bf[DB_WN];
+#pragma unroll
+      for (int bm = 0; bm < DB_WM; ++bm)
+        af[bm] = *reinterpret_cast<const f16x8*>(&cA[(wm * 32 * DB_WM + bm * 32 + (lane & 31)) * BG_LDK + koff]);
+#pragma unroll
+      for (int bn = 0; bn < DB_WN; ++bn) {
+        const int np = wn * 32 * DB_WN + bn * 32 + (lane & 31);
+        uint4 raw = *reinterpret_cast<const uint4*>(&cB[(np >> 1) * BG_LDK + koff]);
+        bf[bn] = bprime_frag(raw, np & 1);
+      }
+#pragma unroll
+      for (int bn = 0; bn < DB_WN; ++bn)
+#pragma unroll
+        for (int bm = 0; bm < DB_WM; ++bm)
+          acc[bn][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[bn], af[bm], acc[bn][bm], 0, 0, 0);
+    }
+    // the other buffer was last read before the previous barrier
+    if (t + 1 < T) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  TO* C = static_cast<TO*>(a.C);
+  float lmax = 0.0f;
+  unsigned lsat = 0;
+#pragma unroll
+  for (int bn = 0; bn < DB_WN; ++bn)
+#pragma unroll
+    for (int bm = 0; bm < DB_WM; ++bm) {
+      const int ml = wm * 32 * DB_WM + bm * 32 + (lane & 31);
+      if (ml >= validM) continue;
+      const int64_t cb = czv + cmT[ml];
+#pragma unroll
+      for (int v = 0; v < 16; v += 2) {
+        const int np = wn * 32 * DB_WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int nl = np >> 1;
         if (nl >= validN) continue;
         const float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
@@ -457,6 +736,9 @@ bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
   if (kernel == K_THIN) return true;
   if (kernel == K_MFMA) return nm >= 5 && nn >= 4;
   if (kernel == K_MFMA_BIG) return in_dt == 1 && nm >= 7 && nn >= 5;
+  if (kernel == K_MFMA_WIDE) return in_dt == 1 && nm >= 7 && nn >= 6;
+  if (kernel == K_MFMA_DB) return in_dt == 1 && nm >= 7 && nn >= 6;
+  if (kernel == K_NARROW) return nm >= 8 && nk <= 6 && nn <= 8 && nn + nk <= 8;
   return false;
 }
 
@@ -472,6 +754,7 @@ static hipError_t launch_thin(const GettArgs& a, hipStream_t s) {
 template <typename TI, typename TO>
 static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
   if (kernel == K_THIN) return launch_thin<TI, TI, TO>(a, s);
+  if (kernel == K_NARROW) return launch_narrow<TI, TI, TO>(a, s);
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn;
   if (kernel == K_MFMA) {
     const int64_t blocks = (int64_t(1) << a.nz) * ((M + MF_BM - 1) / MF_BM) * ((N + MF_BN - 1) / MF_BN);
@@ -479,9 +762,21 @@ static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((gett_mfma<TI, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
   } else {
     if constexpr (std::is_same<TI, _Float16>::value) {
-      const int64_t blocks = (int64_t(1) << a.nz) * ((M + BG_BM - 1) / BG_BM) * ((N + BG_BN - 1) / BG_BN);
-      if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((gett_mfma_big<TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+      if (kernel == K_MFMA_BIG) {
+        using T = BigTile<4, 2>;
+        const int64_t blocks = (int64_t(1) << a.nz) * ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((gett_mfma_big<TO, 4, 2, 2>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+      } else if (kernel == K_MFMA_DB) {
+        const int64_t blocks = (int64_t(1) << a.nz) * ((M + DB_BM - 1) / DB_BM) * ((N + DB_BN - 1) / DB_BN);
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((gett_mfma_db<TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+      } else {
+        using T = BigTile<4, 4>;
+        const int64_t blocks = (int64_t(1) << a.nz) * ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((gett_mfma_big<TO, 4, 4, 1>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+      }
     } else {
       return hipErrorInvalidValue;
     }
@@ -493,6 +788,8 @@ hipError_t launch_gett(int kernel, int a_dt, int b_dt, int out_dt, const GettArg
   if (a_dt != b_dt) {
     // mixed operands: complex-half A with a complex64 B, streaming kernel only
     if (a_dt != 1 || b_dt != 0) return hipErrorInvalidValue;
+    if (kernel == K_NARROW && kernel_applicable(K_NARROW, 1, a.nz, a.nm, a.nn, a.nk))
+      return out_dt ? launch_narrow<_Float16, float, _Float16>(a, s) : launch_narrow<_Float16, float, float>(a, s);
     return out_dt ? launch_thin<_Float16, float, _Float16>(a, s) : launch_thin<_Float16, float, float>(a, s);
   }
   const int in_dt = a_dt;

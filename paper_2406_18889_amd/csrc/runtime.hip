@@ -23,12 +23,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <array>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/leapfrog.h"
@@ -272,6 +274,7 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 // Shape rule used until the autotuner has measured a shape.
 int default_kernel(int dtype, int nz, int nm, int nn, int nk) {
+  if (kernel_applicable(K_NARROW, dtype, nz, nm, nn, nk)) return K_NARROW;
   if (dtype == 1 && nk >= 3 && kernel_applicable(K_MFMA_BIG, dtype, nz, nm, nn, nk)) return K_MFMA_BIG;
   if (nk >= 2 && kernel_applicable(K_MFMA, dtype, nz, nm, nn, nk)) return K_MFMA;
   return K_THIN;
@@ -280,7 +283,7 @@ int default_kernel(int dtype, int nz, int nm, int nn, int nk) {
 // Autotuner results shared by all plans of the process: fastest kernel per
 // (nz, nm, nn, nk, compute type, result type).
 std::mutex g_tune_mu;
-std::map<std::array<int, 6>, int> g_tune;
+std::map<std::array<int, 7>, int> g_tune;
 
 GettArgs step_args(const lf_plan* P, int s) {
   const StepLayout& st = P->hp.steps[s];
@@ -303,7 +306,10 @@ GettArgs step_args(const lf_plan* P, int s) {
   if (P->store_dt[st.out] == 1) a.scale = std::ldexp(1.0f, P->shift[s]);
   else a.scale = std::ldexp(1.0f, ea + eb);
   a.amax_only = 0;
-  a.amax = reinterpret_cast<float*>(P->ws + P->off_amax) + s;
+  // the running maximum is recorded only by the calibration pass: one
+  // atomic per wave on a single word serialises in L2 and would dominate
+  // the time of streaming steps over millions of rows
+  a.amax = nullptr;
   a.sat = reinterpret_cast<unsigned*>(P->ws + P->off_sat);
   return a;
 }
@@ -338,6 +344,7 @@ lf_status calibrate(lf_plan* P, int64_t sigma, hipStream_t stream) {
       GettArgs a = step_args(P, int(s));
       a.scale = 1.0f;
       a.amax_only = 1;
+      a.amax = amax_dev + s;
       HIPCHK(launch_zero_u32(reinterpret_cast<unsigned*>(amax_dev + s), 1, stream));
       HIPCHK(launch_gett(st.kernel, P->store_dt[st.a], P->store_dt[st.b], 1, a, stream));
       float mx = 0;
@@ -477,8 +484,10 @@ lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits
     }
     if (int(P->hp.sliced.size()) > 62) return fail(LF_PLAN_INFEASIBLE, "too many sliced wires");
     // default kernel choice
-    for (auto& s : P->hp.steps)
-      s.kernel = s.b_dtype != s.dtype ? lf::K_THIN : default_kernel(s.dtype, s.nz, s.nm, s.nn, s.nk);
+    for (auto& s : P->hp.steps) {
+      s.kernel = default_kernel(s.dtype, s.nz, s.nm, s.nn, s.nk);
+      if (s.b_dtype != s.dtype && s.kernel != lf::K_NARROW) s.kernel = lf::K_THIN;
+    }
     for (auto& s : P->hp.steps)
       if (s.nz > lf::MAXZ || s.nm > lf::MAXMN || s.nn > lf::MAXMN)
         return fail(LF_PLAN_INFEASIBLE, "step rank exceeds kernel limits");
@@ -553,6 +562,16 @@ lf_status lf_plan_steps(const lf_plan* P, int32_t* dims, double* macs, double* b
     if (macs) macs[s] = st.macs;
     if (bytes) bytes[s] = st.bytes;
   }
+  return LF_OK;
+}
+
+lf_status lf_plan_step_strides(const lf_plan* P, int32_t step, int64_t* out) {
+  if (!P || !out || step < 0 || step >= int32_t(P->hp.steps.size())) return fail(LF_INVALID_ARGUMENT, "bad argument");
+  const lf::StepLayout& st = P->hp.steps[step];
+  int o = 0;
+  for (auto v : st.cz) out[o++] = v;
+  for (auto v : st.cm) out[o++] = v;
+  for (auto v : st.cn) out[o++] = v;
   return LF_OK;
 }
 
@@ -650,22 +669,24 @@ static lf_status autotune(lf_plan* P, int64_t sigma, hipStream_t st) {
   lf_status r = LF_OK;
   for (size_t s = 0; s < P->hp.steps.size() && r == LF_OK; ++s) {
     StepLayout& stp = P->hp.steps[s];
-    std::array<int, 6> key{stp.nz, stp.nm, stp.nn, stp.nk, stp.dtype, P->store_dt[stp.out]};
+    std::array<int, 7> key{stp.nz, stp.nm, stp.nn, stp.nk, P->store_dt[stp.a], P->store_dt[stp.b],
+                           P->store_dt[stp.out]};
     int known = -1;
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune.find(key);
       if (it != g_tune.end()) known = it->second;
     }
-    if (P->store_dt[stp.a] != P->store_dt[stp.b]) known = K_THIN;  // mixed operands
+    const bool mixed = P->store_dt[stp.a] != P->store_dt[stp.b];  // streaming kernels only
     if (known < 0) {
       float best = 1e30f;
       int bestk = stp.kernel;
       bool any_tile = false;
       for (int k = 1; k < K_COUNT; ++k)
-        any_tile |= kernel_applicable(k, stp.dtype, stp.nz, stp.nm, stp.nn, stp.nk);
+        any_tile |= k != K_NARROW && kernel_applicable(k, stp.dtype, stp.nz, stp.nm, stp.nn, stp.nk);
       for (int k = 0; k < K_COUNT && r == LF_OK; ++k) {
         if (!kernel_applicable(k, stp.dtype, stp.nz, stp.nm, stp.nn, stp.nk)) continue;
+        if (mixed && k != K_THIN && k != K_NARROW) continue;
         // the streaming kernel is a candidate only for a narrow side
         if (k == K_THIN && any_tile && stp.nn + stp.nk > 10) continue;
         stp.kernel = k;
@@ -787,6 +808,170 @@ lf_status lf_contract_slices(lf_plan* P, int64_t s0, int64_t s1, void* out_amps,
   return LF_OK;
 }
 
+namespace {
+struct BatchGraph {
+  std::vector<std::tuple<lf_plan*, int64_t, int64_t, void*>> key;
+  int lanes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+};
+std::mutex g_batch_mu;
+BatchGraph g_batch;
+std::map<std::vector<lf_plan*>, int> g_lane_choice;  // tuned lanes per set of plans
+
+lf_status record_batch(const lf_batch_item* items, int n, int lanes, BatchGraph& bg) {
+  bg.release();
+  while (int(bg.streams.size()) < lanes) {
+    hipStream_t s2;
+    HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    bg.streams.push_back(s2);
+  }
+  while (int(bg.events.size()) < 2 * lanes + 1) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    bg.events.push_back(e);
+  }
+  // chains: items grouped by plan in first-appearance order, assigned to
+  // lanes round-robin
+  std::vector<lf_plan*> order;
+  std::map<lf_plan*, std::vector<int>> chains;
+  for (int i = 0; i < n; ++i) {
+    if (!chains.count(items[i].plan)) order.push_back(items[i].plan);
+    chains[items[i].plan].push_back(i);
+  }
+  hipStream_t origin = bg.streams[0];
+  HIPCHK(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
+  lf_status r = LF_OK;
+  hipEvent_t fork = bg.events[0];
+  if (hipEventRecord(fork, origin) != hipSuccess) r = fail(LF_HIP_ERROR, "capture fork");
+  for (int l = 1; l < lanes && r == LF_OK; ++l)
+    if (hipStreamWaitEvent(bg.streams[l], fork, 0) != hipSuccess) r = fail(LF_HIP_ERROR, "capture fork wait");
+  for (size_t c = 0; c < order.size() && r == LF_OK; ++c) {
+    hipStream_t ls = bg.streams[c % lanes];
+    for (int i : chains[order[c]]) {
+      for (int64_t sg = items[i].slice_begin; sg < items[i].slice_end && r == LF_OK; ++sg)
+        r = run_slice(items[i].plan, nullptr, sg, static_cast<double*>(items[i].out_amps), ls);
+    }
+  }
+  for (int l = 1; l < lanes && r == LF_OK; ++l) {
+    if (hipEventRecord(bg.events[l], bg.streams[l]) != hipSuccess ||
+        hipStreamWaitEvent(origin, bg.events[l], 0) != hipSuccess)
+      r = fail(LF_HIP_ERROR, "capture join");
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(origin, &g);
+  if (r) { if (g) (void)hipGraphDestroy(g); return r; }
+  if (e != hipSuccess) return fail(LF_HIP_ERROR, std::string("end capture: ") + hipGetErrorString(e));
+  bg.graph = g;
+  HIPCHK(hipGraphInstantiate(&bg.exec, g, nullptr, nullptr, 0));
+  bg.lanes = lanes;
+  bg.key.clear();
+  for (int i = 0; i < n; ++i)
+    bg.key.emplace_back(items[i].plan, items[i].slice_begin, items[i].slice_end, items[i].out_amps);
+  return LF_OK;
+}
+}  // namespace
+
+lf_status lf_contract_batch(const lf_batch_item* items, int32_t n, int32_t mode, int32_t lanes,
+                            void* stream) {
+  if (n < 0 || (n > 0 && !items)) return fail(LF_INVALID_ARGUMENT, "items");
+  if (mode != LF_BATCH_SEQUENTIAL && mode != LF_BATCH_GRAPH) return fail(LF_INVALID_ARGUMENT, "mode");
+  if (lanes < 0 || lanes > 8) return fail(LF_INVALID_ARGUMENT, "lanes must be in [0, 8]");
+  hipStream_t st = as_stream(stream);
+  for (int i = 0; i < n; ++i) {
+    lf_plan* P = items[i].plan;
+    if (!P) return fail(LF_INVALID_ARGUMENT, "item without a plan");
+    if (!P->bound) return fail(LF_NOT_BOUND, "item plan has no workspace bound");
+    const int64_t ns = int64_t(1) << P->hp.sliced.size();
+    if (items[i].slice_begin < 0 || items[i].slice_end < items[i].slice_begin || items[i].slice_end > ns)
+      return fail(LF_INVALID_ARGUMENT, "item slice range outside [0, n_slices]");
+    if (!items[i].out_amps && items[i].slice_end > items[i].slice_begin)
+      return fail(LF_INVALID_ARGUMENT, "item out_amps is NULL");
+    lf_status r = ensure_ready(P, items[i].slice_begin, st);
+    if (r) return r;
+  }
+  if (mode == LF_BATCH_SEQUENTIAL) {
+    for (int i = 0; i < n; ++i)
+      for (int64_t sg = items[i].slice_begin; sg < items[i].slice_end; ++sg) {
+        lf_status r = run_slice(items[i].plan, nullptr, sg, static_cast<double*>(items[i].out_amps), st);
+        if (r) return r;
+      }
+    return LF_OK;
+  }
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  std::vector<lf_plan*> pset;
+  for (int i = 0; i < n; ++i) pset.push_back(items[i].plan);
+  std::sort(pset.begin(), pset.end());
+  pset.erase(std::unique(pset.begin(), pset.end()), pset.end());
+  // work issued before this call on `st` must finish before the graph runs
+  // on the same stream: the graph is launched on st, so ordering holds.
+  if (lanes == 0) {
+    auto it = g_lane_choice.find(pset);
+    if (it != g_lane_choice.end()) {
+      lanes = it->second;
+    } else {
+      // time 1, 2 and 4 lanes; the trial runs add into temporary
+      // accumulators (allocated here, freed after), so the caller's
+      // accumulators see the batch exactly once
+      std::vector<lf_batch_item> tmp(items, items + n);
+      std::map<void*, double*> scratch;
+      for (auto& it2 : tmp) {
+        if (!scratch.count(it2.out_amps)) {
+          lf_plan* P = it2.plan;
+          const size_t bytes = size_t(P->net.n_batch << P->net.open_qubits.size()) * 16;
+          double* d = nullptr;
+          HIPCHK(hipMalloc(&d, bytes));
+          scratch[it2.out_amps] = d;
+        }
+        it2.out_amps = scratch[it2.out_amps];
+      }
+      float best = 1e30f;
+      int bestl = 1;
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      for (int l : {1, 2, 4}) {
+        lf_status r = record_batch(tmp.data(), n, l, g_batch);
+        if (r) return r;
+        HIPCHK(hipGraphLaunch(g_batch.exec, st));  // warm-up
+        HIPCHK(hipEventRecord(e0, st));
+        HIPCHK(hipGraphLaunch(g_batch.exec, st));
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; bestl = l; }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      g_batch.release();
+      g_batch.key.clear();
+      HIPCHK(hipStreamSynchronize(st));
+      for (auto& kv : scratch) (void)hipFree(kv.second);
+      g_lane_choice[pset] = bestl;
+      lanes = bestl;
+    }
+  }
+  bool same = g_batch.exec && g_batch.lanes == lanes && int(g_batch.key.size()) == n;
+  for (int i = 0; same && i < n; ++i)
+    same = g_batch.key[i] == std::make_tuple(items[i].plan, items[i].slice_begin, items[i].slice_end,
+                                             items[i].out_amps);
+  if (!same) {
+    lf_status r = record_batch(items, n, lanes, g_batch);
+    if (r) return r;
+  }
+  HIPCHK(hipGraphLaunch(g_batch.exec, st));
+  return LF_OK;
+}
+
 lf_status lf_postselect_topk(const void* amps, int64_t n_groups, int64_t group_size, int32_t k,
                              int64_t* out_idx, double* out_prob, void* stream) {
   if (n_groups < 0) return fail(LF_INVALID_ARGUMENT, "n_groups < 0");
@@ -824,6 +1009,35 @@ lf_status lf_profile_steps(lf_plan* P, int32_t reps, double* out_ms, void* strea
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return r;
+}
+
+lf_status lf_autotune_save(const char* path) {
+  if (!path) return fail(LF_INVALID_ARGUMENT, "path is NULL");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(LF_INVALID_ARGUMENT, std::string("cannot write ") + path);
+  for (auto& kv : g_tune) {
+    for (int x : kv.first) std::fprintf(f, "%d ", x);
+    std::fprintf(f, "%d\n", kv.second);
+  }
+  std::fclose(f);
+  return LF_OK;
+}
+
+lf_status lf_autotune_load(const char* path) {
+  if (!path) return fail(LF_INVALID_ARGUMENT, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(LF_INVALID_ARGUMENT, std::string("cannot read ") + path);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::array<int, 7> key;
+  int k;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d", &key[0], &key[1], &key[2], &key[3], &key[4],
+                     &key[5], &key[6], &k) == 8) {
+    if (k < 0 || k >= K_COUNT) continue;
+    g_tune[key] = k;
+  }
+  std::fclose(f);
+  return LF_OK;
 }
 
 lf_status lf_contract_pair(int32_t dtype_in, int32_t dtype_out, int32_t kernel, const void* A,

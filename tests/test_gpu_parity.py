@@ -85,16 +85,30 @@ SHAPES = [
     # nz, nm, nn, nk: thin, tails below a tile, multi-tile, batch, K = 1
     (0, 10, 2, 2), (0, 3, 1, 0), (2, 6, 5, 3), (0, 8, 7, 6), (3, 7, 6, 5),
     (0, 9, 6, 9), (1, 4, 4, 1), (0, 5, 4, 4), (0, 12, 8, 4), (0, 8, 6, 1), (2, 7, 5, 0),
-    (0, 9, 7, 2),
+    (0, 9, 7, 2), (1, 9, 3, 3), (0, 8, 0, 6), (2, 8, 4, 0), (0, 13, 2, 2), (0, 10, 4, 4),
+    (1, 8, 8, 0), (1, 10, 9, 3), (0, 9, 8, 3),
 ]
 
 
-@pytest.mark.parametrize("kernel", [0, 1])
+def _applicable(kernel, dt, shape):
+    nz, nm, nn, nk = shape
+    if kernel == 1:
+        return nm >= 5 and nn >= 4
+    if kernel == 2:
+        return dt == "chalf" and nm >= 7 and nn >= 5
+    if kernel == 3:
+        return nm >= 8 and nk <= 6 and nn <= 8 and nn + nk <= 8
+    if kernel in (4, 5):
+        return dt == "chalf" and nm >= 7 and nn >= 6
+    return True
+
+
+@pytest.mark.parametrize("kernel", [0, 1, 3])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_pair_c64(lf, kernel, shape):
     nz, nm, nn, nk = shape
-    if kernel == 1 and not (nm >= 5 and nn >= 4):
-        pytest.skip("MFMA tile needs nm >= 5 and nn >= 4")
+    if not _applicable(kernel, "c64", shape):
+        pytest.skip("kernel variant not applicable to this shape")
     _say(f"pair c64 kernel={kernel} shape={shape}")
     A = wl.random_complex((1 << (nz + nm + nk),), seed=1 + sum(shape)).astype(np.complex64)
     B = wl.random_complex((1 << (nz + nn + nk),), seed=2 + sum(shape)).astype(np.complex64)
@@ -113,14 +127,12 @@ def _to_half_pairs(x, e):
     return torch.from_numpy(v.astype(np.float16)).cuda()
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_pair_chalf(lf, kernel, shape):
     nz, nm, nn, nk = shape
-    if kernel == 1 and not (nm >= 5 and nn >= 4):
-        pytest.skip("MFMA tile needs nm >= 5 and nn >= 4")
-    if kernel == 2 and not (nm >= 7 and nn >= 5):
-        pytest.skip("large MFMA tile needs nm >= 7 and nn >= 5")
+    if not _applicable(kernel, "chalf", shape):
+        pytest.skip("kernel variant not applicable to this shape")
     _say(f"pair chalf kernel={kernel} shape={shape}")
     A = wl.random_complex((1 << (nz + nm + nk),), seed=11 + sum(shape))
     B = wl.random_complex((1 << (nz + nn + nk),), seed=12 + sum(shape))
@@ -343,3 +355,97 @@ def test_rqc30_full_sum_complex_half(lf):
     e, f = rel_err(got, ref), fidelity(got, ref)
     _say(f"rqc30 chalf rel_err={e:.2e} fidelity={f:.6f} half_steps={plan.info()['n_half_steps']}")
     assert e < CHALF_TOL and f >= 0.999
+
+
+# ------------------------------------------------- batched uneven subtasks
+def test_batch_graph_matches_sequential(lf):
+    """Many subtasks of uneven shape from several circuits: one recorded
+    graph with parallel lanes gives bit-identical accumulators to per-item
+    launches, and both equal per-plan contract calls in item order; each
+    accumulator equals the oracle's projector state vector for its slices."""
+    circuits, subtasks = wl.mixed_workload(4, 48, seed=11, small=True)
+    plans = [lf.Plan(c["circuit"], c["open_qubits"], c["closed_bits"], max_log2=c["max_log2"],
+                     dtype="c64").bind() for c in circuits]
+    items_s, items_g = [], []
+    outs_s = [p.new_amplitudes() for p in plans]
+    outs_g = [p.new_amplitudes() for p in plans]
+    outs_r = [p.new_amplitudes() for p in plans]
+    for (k, draw) in subtasks:
+        ns = plans[k].info()["n_slices"]
+        s0 = draw % ns
+        items_s.append((plans[k], s0, s0 + 1, outs_s[k]))
+        items_g.append((plans[k], s0, s0 + 1, outs_g[k]))
+        plans[k].contract(s0, s0 + 1, outs_r[k])
+    lf.contract_batch(items_s, "sequential")
+    lf.contract_batch(items_g, "graph", lanes=2)
+    torch.cuda.synchronize()
+    for k in range(len(plans)):
+        assert torch.equal(outs_s[k], outs_g[k])
+        assert torch.equal(outs_s[k], outs_r[k])
+    # replay the same recorded graph (eager work in between) and tune lanes
+    for o in outs_g:
+        o.zero_()
+    torch.cuda.synchronize()
+    lf.contract_batch(items_g, "graph", lanes=2)
+    torch.cuda.synchronize()
+    for k in range(len(plans)):
+        assert torch.equal(outs_s[k], outs_g[k])
+    for o in outs_g:
+        o.zero_()
+    lf.contract_batch(items_g, "graph", lanes=0)
+    torch.cuda.synchronize()
+    for k in range(len(plans)):
+        assert torch.equal(outs_s[k], outs_g[k])
+    # oracle: each accumulator is a sum of slices (with multiplicity)
+    for k, c in enumerate(circuits[:2]):
+        wires = plans[k].sliced_wires()
+        ref = np.zeros((len(c["closed_bits"]), 1 << len(c["open_qubits"])), np.complex128)
+        for (kk, draw) in subtasks:
+            if kk != k:
+                continue
+            s0 = draw % plans[k].info()["n_slices"]
+            v = tn.slice_values(s0, len(wires))
+            ref += sv.group_amplitudes(c["circuit"], c["open_qubits"], c["closed_bits"],
+                                       [(q, j, x) for (q, j), x in zip(wires, v)])
+        if np.linalg.norm(ref) > 0:
+            assert rel_err(outs_s[k].cpu().numpy(), ref) < C64_TOL
+
+
+# ----------------------------------------------------- 53 qubits, sampled
+@pytest.mark.parametrize("sigma", [0, 3])
+def test_rqc53_slice_vs_oracle_sampled(lf, sigma):
+    """Configuration 3 at full size: slice sigma of the 53-qubit, 20-cycle
+    plan (cap 2^28, 256 closed strings, 10 open qubits) against the oracle's
+    complex128 contraction of the same sliced network for one sampled closed
+    string (all 1024 open values), following the plan's tree as its order.
+    Complex64 to 1e-5; complex-half to 5e-3 with fidelity >= 0.999."""
+    c, o, cb, spec = wl.standard_workload("rqc53")
+    kw = dict(max_log2=spec["max_log2"], sa_iters=4_000_000, search_dtype="chalf",
+              check_overflow=True)
+    p16 = lf.Plan(c, o, cb, dtype="chalf", **kw)
+    p64 = lf.Plan(c, o, cb, dtype="c64", **kw)
+    assert p16.sliced_wires() == p64.sliced_wires()
+    assert p16.info()["max_log2_intermediate"] <= 28
+    b = 37  # sampled closed string
+    _say(f"rqc53 slice {sigma}: oracle for closed string {b}")
+    leaf_canon, steps, base = p16.tree()
+    wires = p16.sliced_wires()
+    leaves = tn.canonical_network(c, o, cb[b:b + 1])
+    leaves = tn.fix_wires(leaves, wires, tn.slice_values(sigma, len(wires)))
+    keep = tn._keep_labels(o)
+    labels, data = tn.contract_tree(leaves, steps, base, keep)
+    order = ([labels.index("b")] if "b" in labels else []) + \
+        [labels.index(("o", int(q))) for q in reversed(list(o))]
+    ref = np.transpose(data, order).reshape(-1)
+    del data, leaves
+    for plan, tol, name in ((p64, C64_TOL, "c64"), (p16, CHALF_TOL, "chalf")):
+        plan.bind()
+        got = plan.contract(sigma, sigma + 1).cpu().numpy()[b]
+        e, f = rel_err(got, ref), fidelity(got, ref)
+        _say(f"rqc53 slice {sigma} {name}: rel_err={e:.2e} fidelity={f:.6f}")
+        assert e < tol
+        if name == "chalf":
+            assert f >= 0.999
+        plan.workspace = None
+        plan.close()
+        torch.cuda.empty_cache()

@@ -24,4 +24,5 @@ from .circuits import (  # noqa: F401
     standard_workload,
     WORKLOADS,
     random_complex,
+    mixed_workload,
 )

@@ -244,3 +244,40 @@ def random_complex(shape, seed: int, dtype=np.complex128) -> np.ndarray:
     re = rng.standard_normal(shape)
     im = rng.standard_normal(shape)
     return ((re + 1j * im) / math.sqrt(2.0)).astype(dtype)
+
+
+MIX_GRIDS = ((5, 6, 0), (6, 6, 0), (6, 7, 0), (7, 7, 0), (6, 9, 1))
+
+
+def mixed_workload(n_circuits: int = 8, n_subtasks: int = 512, seed: int = 4096,
+                   small: bool = False):
+    """Uneven batch of sliced subtasks: `n_circuits` seeded circuits (grids
+    5x6 .. 6x9-1, 12..20 cycles, 6..10 open qubits, 16..256 closed strings,
+    intermediate cap 2^24..2^27) and `n_subtasks` (circuit, slice draw) pairs;
+    the slice draw is reduced modulo the plan's slice count by the caller.
+    `small` uses 4x4..5x5 grids, 8..12 cycles and caps 2^14..2^16 (tests)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    circuits = []
+    for i in range(n_circuits):
+        if small:
+            r, c, rem = [(4, 4, 0), (4, 5, 0), (5, 5, 0)][int(rng.integers(3))]
+            cyc = int(rng.integers(8, 13))
+            n_open = int(rng.integers(3, 6))
+            nb = int(rng.choice([4, 16]))
+            cap = int(rng.integers(14, 17))
+        else:
+            r, c, rem = MIX_GRIDS[int(rng.integers(len(MIX_GRIDS)))]
+            cyc = int(rng.integers(12, 21))
+            n_open = int(rng.integers(6, 11))
+            nb = int(rng.choice([16, 64, 256]))
+            cap = int(rng.integers(24, 28))
+        circ = random_circuit(r, c, cyc, int(rng.integers(1, 1 << 30)), rem,
+                              int(rng.integers(1, 1 << 30)))
+        n = circ.n_qubits
+        openq = list(range(n - n_open, n))
+        cb = closed_bitstrings(n, openq, nb, int(rng.integers(1, 1 << 30)))
+        circuits.append(dict(circuit=circ, open_qubits=np.array(openq, np.int32),
+                             closed_bits=cb, max_log2=cap, grid=(r, c, rem), cycles=cyc))
+    subtasks = [(int(rng.integers(n_circuits)), int(rng.integers(0, 1 << 62)))
+                for _ in range(n_subtasks)]
+    return circuits, subtasks
