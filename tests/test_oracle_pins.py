@@ -5,6 +5,7 @@ CPU only.
 """
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -266,3 +267,19 @@ def test_partial_sum_fidelity_tracks_fraction():
             ov = abs(np.vdot(psi, psi_d)) ** 2 / (sv.norm2(psi) * sv.norm2(psi_d))
             fids.append(ov)
         assert abs(np.mean(fids) / 2.0 ** -D - 1.0) < 0.3
+
+
+def test_golden_prefix_fidelity_is_the_fraction():
+    """Methods A / Eq. 3: keeping a fraction f = 2^-D of the slices gives
+    amplitudes whose fidelity with the exact ones is about f (random
+    circuits: the dropped slices are nearly orthogonal to the kept ones).
+    Checks the stored 30-qubit prefix sums (256 x 64 amplitudes) against the
+    stored exact amplitudes, and that each prefix is about the fraction f of
+    the exact squared norm."""
+    gold = os.path.join(os.path.dirname(__file__), "golden")
+    ex = np.load(os.path.join(gold, "rqc30_exact.npy")).reshape(-1)
+    for D in range(1, 6):
+        pre = np.load(os.path.join(gold, f"rqc30_prefix_D{D}.npy")).reshape(-1)
+        f = abs(np.vdot(ex, pre)) ** 2 / (np.vdot(ex, ex).real * np.vdot(pre, pre).real)
+        assert abs(f * 2 ** D - 1) < 0.05, (D, f)
+        assert abs(np.vdot(pre, pre).real / np.vdot(ex, ex).real * 2 ** D - 1) < 0.1, D
