@@ -5,7 +5,7 @@ amplitude accumulator and runs the top-k post-selection on it (the whole hot
 path).  Inputs (plan, leaves, workspace) are resident in HBM before timing.
 Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rqc30|rqc53]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rqc30|rqc53|mix512]
                   [--dtype chalf|c64] [--slices-per-step S]
 """
 
@@ -21,10 +21,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MI355X = {"hbm_gbs": 8000.0, "fp16_tflops": 2500.0, "fp32_tflops": 157.3}
-# kernel ids of the contraction steps; the two large tiles are one template
-# (gett_mfma_big<TO, WM, WN, MINB>) with 4x2 and 4x4 wave layouts
-KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big<4,2,2>", 3: "gett_narrow",
-                4: "gett_mfma_big<4,4,1>"}
+# kernel ids of the contraction steps; the large tiles are instances of
+# gett_mfma_big<TO, WM, WN, MINB, ST, BK, FULL>, named here by WM,WN,MINB,ST,BK
+KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big<4,2,2,1,32>", 3: "gett_narrow",
+                4: "gett_mfma_big<4,4,1,1,32>", 5: "gett_mfma_big<4,4,1,2,32>",
+                6: "gett_mfma_big<4,4,1,1,64>", 7: "gett_skinny"}
 # planner settings per workload (search effort, not inputs)
 PLAN_OPTS = {"rqc53": {"sa_iters": 4_000_000}}
 
@@ -121,11 +122,96 @@ def cpu_baseline(plan, circ, openq, cb, seconds):
                       f"multiply-adds and multiplied by {len(cb)} strings"}
 
 
+def run_mix(args):
+    """The batched uneven workload: 512 sliced subtasks (one slice each) of
+    8 seeded circuits (30..53 qubits, 12..20 cycles, caps 2^24..2^27), all
+    contracted by one recorded graph launch per step, then the per-circuit
+    top-1 post-selection.  Also times the same items launched one slice
+    after another (no graph) and the other arithmetic."""
+    import numpy as np
+    import torch
+
+    import paper_2406_18889_amd as lf
+    import workloads as wl
+
+    circuits, subtasks = wl.mixed_workload()
+
+    def plans_for(dtype):
+        ps = [lf.Plan(c["circuit"], c["open_qubits"], c["closed_bits"], max_log2=c["max_log2"],
+                      dtype=dtype, search_dtype="chalf", check_overflow=False).bind()
+              for c in circuits]
+        outs = [p.new_amplitudes() for p in ps]
+        items = []
+        for (k, draw) in subtasks:
+            s0 = draw % ps[k].info()["n_slices"]
+            items.append((ps[k], s0, s0 + 1, outs[k]))
+        return ps, outs, items
+
+    def timed(items, outs, mode, steps, warmup):
+        def one():
+            lf.contract_batch(items, mode)
+            for o, c in zip(outs, circuits):
+                lf.postselect_topk(o, 1 << len(c["open_qubits"]), 1)
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    ps, outs, items = plans_for(args.dtype)
+    macs = sum(ps[k].info()["macs_per_slice"] for (k, _) in subtasks)
+    dt = timed(items, outs, "graph", args.steps, max(1, args.warmup))
+    dt_seq = timed(items, outs, "sequential", max(1, min(args.steps, 3)), 1)
+    value = len(items) / dt
+    out = {
+        "metric": "sliced-subtask contractions/s",
+        "value": value, "unit": "subtasks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": max(1, args.warmup), "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "chalf" if args.dtype == "chalf" else "c64", "data": "synthetic",
+        "config": {"workload": "mix512", "subtasks": len(items), "circuits": len(circuits),
+                   "grids": [list(c["grid"]) for c in circuits],
+                   "cycles": [c["cycles"] for c in circuits],
+                   "caps_log2": [c["max_log2"] for c in circuits]},
+        "algorithmic_tflops": 8.0 * macs / dt / 1e12,
+        "mfma_frac_algorithmic": 8.0 * macs / dt / 1e12 /
+                                  (MI355X["fp16_tflops"] if args.dtype == "chalf" else MI355X["fp32_tflops"]),
+        "sequential": {"value": len(items) / dt_seq, "unit": "subtasks/s",
+                       "graph_speedup": dt_seq / dt},
+    }
+    if args.compare and args.compare not in ("none", args.dtype):
+        for o in outs:
+            o.zero_()
+        lf.contract_batch(items, "graph")
+        torch.cuda.synchronize()
+        a = [o.cpu().numpy() for o in outs]
+        del ps, outs, items
+        torch.cuda.empty_cache()
+        ps2, outs2, items2 = plans_for(args.compare)
+        dt2 = timed(items2, outs2, "graph", max(1, min(args.steps, 3)), 1)
+        for o in outs2:
+            o.zero_()
+        lf.contract_batch(items2, "graph")
+        torch.cuda.synchronize()
+        x = np.concatenate([v.reshape(-1) for v in a])
+        y = np.concatenate([o.cpu().numpy().reshape(-1) for o in outs2])
+        rel = float(np.linalg.norm(x - y) / np.linalg.norm(y))
+        fid = float(abs(np.vdot(y, x)) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real))
+        out["compare"] = {"dtype": args.compare, "value": len(items2) / dt2, "unit": "subtasks/s",
+                          "speedup": dt2 / dt, "rel_err_vs_compare": rel, "fidelity_vs_compare": fid}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "mix512":
+        return run_mix(args)
     import numpy as np
     import torch
 
@@ -166,6 +252,20 @@ def main():
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
+    if not args.trace:
+        # isolated per-step timing (outside the timed region) picks the
+        # dominant kernel: the variant with the largest total time per slice
+        ms = plan.profile_steps(reps=3)
+        dims, macs, byts = plan.steps()
+        var = dims[:, 4] == 1
+        kinds = sorted(set(int(k) for k in dims[var, 7]))
+        tot = {k: float(ms[var & (dims[:, 7] == k)].sum()) for k in kinds}
+        dom_k = max(tot, key=tot.get)
+        sel = var & (dims[:, 7] == dom_k)
+        # its launches in the timed region are bracketed by HIP events on the
+        # plan's launch stream
+        plan.time_kernel(dom_k, reserve=int(sel.sum()) * S * args.steps)
+        plan.kernel_times()
     t0 = time.perf_counter()
     done = 0
     for i in range(args.steps):
@@ -181,19 +281,14 @@ def main():
                           "source_hash": source_hash()}))
         return
 
-    # per-step kernel timing (HIP events on the plan's stream); the dominant
-    # kernel is the variant with the largest total time per slice, reported
-    # over all of its launches in a slice (as a per-kernel profiler does)
-    ms = plan.profile_steps(reps=3)
-    dims, macs, byts = plan.steps()
-    var = dims[:, 4] == 1
-    kinds = sorted(set(int(k) for k in dims[var, 7]))
-    tot = {k: float(ms[var & (dims[:, 7] == k)].sum()) for k in kinds}
-    dom_k = max(tot, key=tot.get)
-    sel = var & (dims[:, 7] == dom_k)
-    t = float(ms[sel].sum()) * 1e-3
-    flops = 8.0 * float(macs[sel].sum())
-    bytes_ = float(byts[sel].sum())
+    # the dominant kernel over its launches in the timed region: algorithmic
+    # flops (8 per complex multiply-add) and bytes of the launched steps over
+    # their summed event-timed durations
+    tot_ms, n_launch, per_ms, per_n = plan.kernel_times()
+    plan.time_kernel(-1)
+    t = tot_ms * 1e-3
+    flops = 8.0 * float((macs * per_n).sum())
+    bytes_ = float((byts * per_n).sum())
     half = bool((dims[sel, 5] == 1).all())
     peak_tf = MI355X["fp16_tflops"] if half else MI355X["fp32_tflops"]
     ridge = peak_tf * 1e12 / (MI355X["hbm_gbs"] * 1e9)
@@ -204,11 +299,14 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = traffic_for(args.workload, args.dtype, KERNEL_NAMES.get(dom_k, "?"))
     roof["kernel"] = {"name": KERNEL_NAMES.get(dom_k, "?"), "launches_per_slice": int(sel.sum()),
-                      "avg_launch_ms": float(ms[sel].mean()),
-                      "algorithmic_flop_per_launch": flops / int(sel.sum()),
-                      "algorithmic_bytes_per_launch": bytes_ / int(sel.sum()),
-                      "share_of_slice": tot[dom_k] / sum(tot.values())}
-    roof["by_kernel_ms_per_slice"] = {KERNEL_NAMES.get(k, "?"): v for k, v in tot.items()}
+                      "timed_launches": int(n_launch),
+                      "avg_launch_ms": tot_ms / max(1, n_launch),
+                      "algorithmic_flop_per_launch": flops / max(1, n_launch),
+                      "algorithmic_bytes_per_launch": bytes_ / max(1, n_launch),
+                      "share_of_slice_time": tot_ms / max(1, n_launch) * int(sel.sum()) /
+                                             (dt / done * 1e3)}
+    # isolated per-step timings (3 repetitions each), summed per kernel
+    roof["isolated_ms_per_slice_by_kernel"] = {KERNEL_NAMES.get(k, "?"): v for k, v in tot.items()}
     if args.dump_steps:
         with open(args.dump_steps, "w") as f:
             json.dump({"dims": dims.tolist(), "macs": macs.tolist(), "bytes": byts.tolist(),

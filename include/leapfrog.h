@@ -233,21 +233,49 @@ lf_status lf_postselect_topk(const void* amps, int64_t n_groups, int64_t group_s
 lf_status lf_profile_steps(lf_plan* plan, int32_t reps, double* out_ms, void* stream);
 
 /*
+ * Live timing of one contraction kernel inside lf_contract_slices (not a
+ * step of the method: instrumentation for measuring the steps where they
+ * run).  After lf_plan_time_kernel(plan, kernel, reserve), every launch of
+ * the steps whose kernel id (dims[7] of lf_plan_steps) equals `kernel` is
+ * bracketed by a pair of HIP events on the caller's stream, in stream launch
+ * mode only (graph launches are not timed).  `reserve` pre-creates events
+ * for that many launches so that none is created while timing; more are
+ * created on demand.  kernel -1 switches timing off.  Errors:
+ * LF_INVALID_ARGUMENT (kernel id, reserve outside [0, 2^20]), LF_HIP_ERROR.
+ *
+ * lf_plan_kernel_times waits for the last timed launch and returns the
+ * milliseconds summed over the launches timed since the previous call and
+ * their count; per_step_ms and per_step_launches (nullable host arrays of
+ * n_steps) receive the same per step.  The counters then restart.
+ */
+lf_status lf_plan_time_kernel(lf_plan* plan, int32_t kernel, int64_t reserve);
+lf_status lf_plan_kernel_times(lf_plan* plan, double* total_ms, int64_t* launches,
+                               double* per_step_ms, int64_t* per_step_launches);
+
+/*
  * One pairwise complex contraction, the operation every step of a plan
  * performs (Methods C):  C[z,m,n] = scale * sum_k A[z,m,k] * B[z,n,k]  over
- * 2^nz x 2^nm x 2^nn x 2^nk.  A is a row-major [2^nz][2^nm][2^nk] array and B
- * a row-major [2^nz][2^nn][2^nk] array of (re, im) pairs in dtype_in; C
+ * 2^nz x 2^nm x 2^nn x 2^nk.  A is a row-major [2^nz][2^nm][2^nk] array of
+ * (re, im) pairs in dtype_a and B a row-major [2^nz][2^nn][2^nk] array in
+ * dtype_b (equal, or a complex-half A with a complex64 B); C
  * element (z,m,n) is written, in dtype_out, at element offset
  * sum_b bit_b(z) c_strides[b] + sum_b bit_b(m) c_strides[nz+b] +
  * sum_b bit_b(n) c_strides[nz+nm+b]; the strides must map distinct (z,m,n)
- * to distinct elements.  kernel: 0 streaming (narrow side), 1 MFMA tile,
- * -1 the plan's default choice.  Device pointers owned by the caller; A and
+ * to distinct elements.  kernel: 0 streaming (one row per thread), 1 MFMA
+ * 128 x 64 complex tile, 2 MFMA 256 x 64 tile (complex-half), 3 streaming
+ * with B staged in LDS (2^nn 2^nk <= 256, 2^nm >= 256), 4 MFMA 256 x 128
+ * tile (complex-half), 5 the 256 x 128 tile with double-buffered LDS
+ * (complex-half), 6 the 256 x 128 tile with 64-deep K steps (complex-half),
+ * 7 MFMA on 32-row groups against a B of 2^nn <= 16 rows held in registers
+ * (complex-half A, 2 <= nk <= 6), -1 the default choice; a kernel that does
+ * not apply to the
+ * shape or dtype falls back to 0.  Device pointers owned by the caller; A and
  * B 16-byte aligned.  Limits: nz <= 20, nm, nn <= 40.  Errors:
  * LF_INVALID_ARGUMENT, LF_HIP_ERROR.
  */
-lf_status lf_contract_pair(int32_t dtype_in, int32_t dtype_out, int32_t kernel, const void* A,
-                           const void* B, void* C, int32_t nz, int32_t nm, int32_t nn, int32_t nk,
-                           const int64_t* c_strides, float scale, void* stream);
+lf_status lf_contract_pair(int32_t dtype_a, int32_t dtype_b, int32_t dtype_out, int32_t kernel,
+                           const void* A, const void* B, void* C, int32_t nz, int32_t nm, int32_t nn,
+                           int32_t nk, const int64_t* c_strides, float scale, void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned step-cost model (planner extension): a three-layer perceptron

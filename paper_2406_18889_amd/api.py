@@ -178,6 +178,26 @@ class Plan:
                                          _stream_ptr(stream)), "lf_profile_steps")
         return out[:S]
 
+    def time_kernel(self, kernel: int, reserve: int = 0):
+        """Bracket every launch of contraction kernel `kernel` with HIP events
+        in later stream-mode contractions (-1: off)."""
+        check(self._lib.lf_plan_time_kernel(self._handle, int(kernel), int(reserve)),
+              "lf_plan_time_kernel")
+
+    def kernel_times(self):
+        """(total_ms, launches, per_step_ms, per_step_launches) of the launches
+        timed since the previous call."""
+        S = self.info()["n_steps"]
+        per_ms = np.zeros(max(1, S))
+        per_n = np.zeros(max(1, S), np.int64)
+        tot = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(self._lib.lf_plan_kernel_times(self._handle, ctypes.byref(tot), ctypes.byref(n),
+                                             per_ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             per_n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+              "lf_plan_kernel_times")
+        return tot.value, n.value, per_ms[:S], per_n[:S]
+
     def close(self):
         if getattr(self, "_handle", None) and self._handle.value:
             self._lib.lf_plan_destroy(self._handle)
@@ -233,7 +253,8 @@ def contract_pair(A, B, C, nz: int, nm: int, nn: int, nk: int, c_strides, scale:
                   kernel: int = -1, stream=None):
     """lf_contract_pair on device tensors.  A, B, C are torch tensors holding
     (re, im) pairs: complex64 (float32 pairs) or complex-half (float16 pairs
-    with a trailing dimension of 2)."""
+    with a trailing dimension of 2); A and B share a dtype, or A is
+    complex-half and B complex64."""
     import torch
 
     def dt(t):
@@ -243,12 +264,12 @@ def contract_pair(A, B, C, nz: int, nm: int, nn: int, nk: int, c_strides, scale:
             return _lib.LF_CHALF
         raise ValueError("tensors must be complex64 or float16 pairs")
 
-    if dt(A) != dt(B):
-        raise ValueError("A and B must share a dtype")
+    if dt(A) != dt(B) and not (dt(A) == _lib.LF_CHALF and dt(B) == _lib.LF_C64):
+        raise ValueError("A and B must share a dtype, or be complex-half A and complex64 B")
     st = np.ascontiguousarray(np.asarray(c_strides, np.int64))
     if st.size != nz + nm + nn:
         raise ValueError("need nz + nm + nn strides")
-    check(_lib.load().lf_contract_pair(dt(A), dt(C), kernel, ctypes.c_void_p(A.data_ptr()),
+    check(_lib.load().lf_contract_pair(dt(A), dt(B), dt(C), kernel, ctypes.c_void_p(A.data_ptr()),
                                        ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()),
                                        nz, nm, nn, nk,
                                        st.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),

@@ -202,47 +202,71 @@ def flopmem_seconds(dims: np.ndarray) -> np.ndarray:
 
 # ------------------------------------------------------------- collection
 def collect(target_steps: int = 50_000, seed: int = 0, reps: int = 2, log=print,
-            time_budget: float = 1e9) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+            time_budget: float = 1e9, workers: int = 12,
+            sa_iters: int = 200_000) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """Times every step of many plans for 53-qubit, 20-cycle circuits (other
-    circuit seeds, caps 2^20..2^28, both arithmetics) with the library's
-    per-step HIP-event profiler.  Returns (features, log seconds, dims)."""
+    circuit seeds, caps 2^27..2^30, both arithmetics, 1/16/256 closed
+    strings) with the library's per-step HIP-event profiler.  Plans are
+    searched on `workers` host threads (the planner runs outside the
+    interpreter lock) while the GPU profiles the previous ones.  Returns
+    (features, log seconds, dims)."""
+    import concurrent.futures as cf
+
     import torch
 
     import workloads as wl
     from .api import Plan
 
     rng = np.random.Generator(np.random.PCG64(seed))
+
+    def spec(k):
+        cseed = int(rng.integers(1, 1 << 30))
+        cap = int(rng.integers(27, 31))   # below 2^27 the search rarely fits
+        nb = int(rng.choice([1, 16, 256]))
+        return dict(k=k, cseed=cseed, cap=cap, dtype="chalf" if k % 2 else "c64", nb=nb,
+                    rem=int(rng.integers(1, 1000)), bseed=int(rng.integers(1, 1 << 30)),
+                    pseed=int(rng.integers(1, 1 << 30)))
+
+    def make(sp):
+        circ = wl.random_circuit(6, 9, 20, sp["cseed"], 1, sp["rem"])
+        openq = list(range(circ.n_qubits - 10, circ.n_qubits))
+        cb = wl.closed_bitstrings(circ.n_qubits, openq, sp["nb"], sp["bseed"])
+        try:
+            return Plan(circ, openq, cb, dtype=sp["dtype"], max_log2=sp["cap"], sa_iters=sa_iters,
+                        seed=sp["pseed"], check_overflow=False)
+        except Exception as e:  # infeasible at this cap
+            return e
+
     Xs, ts, ds = [], [], []
     n = 0
     t0 = time.time()
     k = 0
-    while n < target_steps and time.time() - t0 < time_budget:
-        cseed = int(rng.integers(1, 1 << 30))
-        cap = int(rng.integers(20, 29))
-        dtype = "chalf" if k % 2 else "c64"
-        nb = int(rng.choice([1, 16, 256]))
-        circ = wl.random_circuit(6, 9, 20, cseed, 1, int(rng.integers(1, 1000)))
-        openq = list(range(circ.n_qubits - 10, circ.n_qubits))
-        cb = wl.closed_bitstrings(circ.n_qubits, openq, nb, int(rng.integers(1, 1 << 30)))
-        try:
-            plan = Plan(circ, openq, cb, dtype=dtype, max_log2=cap, sa_iters=200_000,
-                        seed=int(rng.integers(1, 1 << 30)), check_overflow=False)
-        except Exception as e:  # infeasible at this cap: skip
-            log(f"plan {k}: {e}")
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        pending = [(sp, ex.submit(make, sp)) for sp in (spec(i) for i in range(2 * workers))]
+        k = len(pending)
+        while pending and n < target_steps and time.time() - t0 < time_budget:
+            sp, fut = pending.pop(0)
+            nxt = spec(k)
+            pending.append((nxt, ex.submit(make, nxt)))
             k += 1
-            continue
-        plan.bind()
-        ms = plan.profile_steps(reps=reps)
-        dims, _, _ = plan.steps()
-        Xs.append(features(dims))
-        ts.append(np.log(np.maximum(ms, 1e-6) * 1e-3))
-        ds.append(dims)
-        n += len(dims)
-        log(f"plan {k}: cap 2^{cap} {dtype} B={nb}: {len(dims)} steps, total {n}")
-        plan.close()
-        del plan
-        torch.cuda.empty_cache()
-        k += 1
+            plan = fut.result()
+            if isinstance(plan, Exception):
+                log(f"plan {sp['k']}: {plan}")
+                continue
+            plan.bind()
+            ms = plan.profile_steps(reps=reps)
+            dims, _, _ = plan.steps()
+            Xs.append(features(dims))
+            ts.append(np.log(np.maximum(ms, 1e-6) * 1e-3))
+            ds.append(dims)
+            n += len(dims)
+            log(f"plan {sp['k']}: cap 2^{sp['cap']} {sp['dtype']} B={sp['nb']}: {len(dims)} steps, "
+                f"total {n} ({time.time() - t0:.0f} s)")
+            plan.close()
+            del plan
+            torch.cuda.empty_cache()
+        for _, fut in pending:
+            fut.cancel()
     return np.concatenate(Xs), np.concatenate(ts), np.concatenate(ds)
 
 

@@ -42,15 +42,19 @@ struct GettArgs {
 // tile (both arithmetics); K_MFMA_BIG: 256 x 64 complex tile, complex-half
 // only; K_NARROW: one row per thread with B staged in LDS, for N K <= 256
 // and M >= 256; K_MFMA_WIDE: 256 x 128 complex tile, complex-half only;
-// K_MFMA_DB: the 256 x 128 tile with double-buffered LDS and an XCD-aware
-// tile order, complex-half only.
+// K_MFMA_DB: the 256 x 128 tile with double-buffered LDS, complex-half
+// only; K_MFMA_DEEP: the 256 x 128 tile with 64-deep K steps (one LDS
+// buffer).  All large tiles walk the tiles in an XCD-aware order.
+// K_SKINNY: MFMA on 32-row groups of A against a B' of at most 32 rows held
+// in registers (N <= 16, 4 <= K <= 64), complex-half A, B either type.
 enum KernelId : int {
-  K_THIN = 0, K_MFMA = 1, K_MFMA_BIG = 2, K_NARROW = 3, K_MFMA_WIDE = 4, K_MFMA_DB = 5, K_COUNT = 6
+  K_THIN = 0, K_MFMA = 1, K_MFMA_BIG = 2, K_NARROW = 3, K_MFMA_WIDE = 4, K_MFMA_DB = 5, K_MFMA_DEEP = 6,
+  K_SKINNY = 7, K_COUNT = 8
 };
 
 // a_dt, b_dt, out_dt: 0 complex64 (float pairs), 1 complex-half (_Float16
 // pairs).  a_dt != b_dt is allowed only as a complex-half A with a
-// complex64 B, on the streaming kernel.
+// complex64 B, on the streaming kernels and K_SKINNY.
 hipError_t launch_gett(int kernel, int a_dt, int b_dt, int out_dt, const GettArgs& a, hipStream_t s);
 bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk);
 

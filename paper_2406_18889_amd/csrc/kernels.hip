@@ -339,65 +339,74 @@ __global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-  for (int64_t k0 = 0; k0 < K; k0 += BK) {
-    // A tile: MF_BM rows x CH_ROW chunks
-    for (int c = tid; c < MF_BM * CH_ROW; c += 256) {
-      const int r = c / CH_ROW, ch = c % CH_ROW;
-      const int64_t kc = k0 + int64_t(ch) * CPC;
-      TI* dst = &sA[r * LDA + 2 * ch * CPC];
-      if (r < validM && kc + CPC <= K) {
-        *reinterpret_cast<float4*>(dst) =
-            *reinterpret_cast<const float4*>(Ab + 2 * (int64_t(r) * K + kc));
-      } else {
+  // full tiles with K a multiple of BK take a copy of the loop without
+  // bounds tests (predicated loads would each be waited for)
+  auto main_loop = [&](auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    for (int64_t k0 = 0; k0 < K; k0 += BK) {
+      // A tile: MF_BM rows x CH_ROW chunks
+      for (int c = tid; c < MF_BM * CH_ROW; c += 256) {
+        const int r = c / CH_ROW, ch = c % CH_ROW;
+        const int64_t kc = k0 + int64_t(ch) * CPC;
+        TI* dst = &sA[r * LDA + 2 * ch * CPC];
+        if (FULL || (r < validM && kc + CPC <= K)) {
+          *reinterpret_cast<float4*>(dst) =
+              *reinterpret_cast<const float4*>(Ab + 2 * (int64_t(r) * K + kc));
+        } else {
 #pragma unroll
-        for (int e = 0; e < CPC; ++e) {
-          const bool ok = r < validM && kc + e < K;
-          dst[2 * e] = ok ? Ab[2 * (int64_t(r) * K + kc + e)] : TI(0);
-          dst[2 * e + 1] = ok ? Ab[2 * (int64_t(r) * K + kc + e) + 1] : TI(0);
+          for (int e = 0; e < CPC; ++e) {
+            const bool ok = r < validM && kc + e < K;
+            dst[2 * e] = ok ? Ab[2 * (int64_t(r) * K + kc + e)] : TI(0);
+            dst[2 * e + 1] = ok ? Ab[2 * (int64_t(r) * K + kc + e) + 1] : TI(0);
+          }
         }
       }
-    }
-    // B tile, expanded to B' rows 2n, 2n+1
-    for (int c = tid; c < MF_BN * CH_ROW; c += 256) {
-      const int r = c / CH_ROW, ch = c % CH_ROW;
-      const int64_t kc = k0 + int64_t(ch) * CPC;
-      TI re[CPC], im[CPC];
-      if (r < validN && kc + CPC <= K) {
-        TI tmp[2 * CPC];
-        *reinterpret_cast<float4*>(tmp) = *reinterpret_cast<const float4*>(Bb + 2 * (int64_t(r) * K + kc));
+      // B tile, expanded to B' rows 2n, 2n+1
+      for (int c = tid; c < MF_BN * CH_ROW; c += 256) {
+        const int r = c / CH_ROW, ch = c % CH_ROW;
+        const int64_t kc = k0 + int64_t(ch) * CPC;
+        TI re[CPC], im[CPC];
+        if (FULL || (r < validN && kc + CPC <= K)) {
+          TI tmp[2 * CPC];
+          *reinterpret_cast<float4*>(tmp) = *reinterpret_cast<const float4*>(Bb + 2 * (int64_t(r) * K + kc));
 #pragma unroll
-        for (int e = 0; e < CPC; ++e) { re[e] = tmp[2 * e]; im[e] = tmp[2 * e + 1]; }
-      } else {
+          for (int e = 0; e < CPC; ++e) { re[e] = tmp[2 * e]; im[e] = tmp[2 * e + 1]; }
+        } else {
+#pragma unroll
+          for (int e = 0; e < CPC; ++e) {
+            const bool ok = r < validN && kc + e < K;
+            re[e] = ok ? Bb[2 * (int64_t(r) * K + kc + e)] : TI(0);
+            im[e] = ok ? Bb[2 * (int64_t(r) * K + kc + e) + 1] : TI(0);
+          }
+        }
+        TI row0[2 * CPC], row1[2 * CPC];
 #pragma unroll
         for (int e = 0; e < CPC; ++e) {
-          const bool ok = r < validN && kc + e < K;
-          re[e] = ok ? Bb[2 * (int64_t(r) * K + kc + e)] : TI(0);
-          im[e] = ok ? Bb[2 * (int64_t(r) * K + kc + e) + 1] : TI(0);
+          row0[2 * e] = re[e];
+          row0[2 * e + 1] = -im[e];
+          row1[2 * e] = im[e];
+          row1[2 * e + 1] = re[e];
         }
+        *reinterpret_cast<float4*>(&sB[(2 * r) * LDA + 2 * ch * CPC]) = *reinterpret_cast<float4*>(row0);
+        *reinterpret_cast<float4*>(&sB[(2 * r + 1) * LDA + 2 * ch * CPC]) = *reinterpret_cast<float4*>(row1);
       }
-      TI row0[2 * CPC], row1[2 * CPC];
+      __syncthreads();
 #pragma unroll
-      for (int e = 0; e < CPC; ++e) {
-        row0[2 * e] = re[e];
-        row0[2 * e + 1] = -im[e];
-        row1[2 * e] = im[e];
-        row1[2 * e + 1] = re[e];
+      for (int kk = 0; kk < BK2; kk += Tr::KS) {
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+          for (int bm = 0; bm < 2; ++bm)
+            acc[bn][bm] = mfma_step<TI>(sB, sA, wn * 64 + bn * 32 + (lane & 31),
+                                        wm * 64 + bm * 32 + (lane & 31), LDA, kk, lane, acc[bn][bm]);
       }
-      *reinterpret_cast<float4*>(&sB[(2 * r) * LDA + 2 * ch * CPC]) = *reinterpret_cast<float4*>(row0);
-      *reinterpret_cast<float4*>(&sB[(2 * r + 1) * LDA + 2 * ch * CPC]) = *reinterpret_cast<float4*>(row1);
+      __syncthreads();
     }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK2; kk += Tr::KS) {
-#pragma unroll
-      for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-        for (int bm = 0; bm < 2; ++bm)
-          acc[bn][bm] = mfma_step<TI>(sB, sA, wn * 64 + bn * 32 + (lane & 31),
-                                      wm * 64 + bm * 32 + (lane & 31), LDA, kk, lane, acc[bn][bm]);
-    }
-    __syncthreads();
-  }
+  };
+  if (validM == MF_BM && validN == MF_BN && K % BK == 0)
+    main_loop(std::integral_constant<bool, true>{});
+  else
+    main_loop(std::integral_constant<bool, false>{});
 
   // epilogue: lane holds column m, rows n' = 8(v/4) + 4(lane/32) + v%4
   TO* C = static_cast<TO*>(a.C);
@@ -423,7 +432,7 @@ __global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
   block_amax_sat(lmax, lsat, a.amax, a.sat);
 }
 
-// ------------------------------------------------ MFMA, large f16 tile
+// ------------------------------------------------ MFMA, large f16 tiles
 // Complex-half operands.  Four waves in 2 (m) x 2 (n) arrangement; each wave
 // owns WM x WN MFMA 32x32x16 blocks (32 WM values of m by 32 WN rows of B',
 // i.e. 16 WN complex n), so the block tile is 64 WM (m) x 32 WN (complex n)
@@ -431,14 +440,45 @@ __global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
 // fragment of a lane is formed in registers from 4 complex values of row
 // n = n'/2: row 2n gets (Br, -Bi), row 2n+1 gets (Bi, Br).  The next K tile
 // is fetched from HBM into registers while the current one is multiplied.
-constexpr int BG_BK = 32;
-constexpr int BG_LDK = 2 * BG_BK + 8;  // halves per LDS row (16 B pad)
+//
+// ST = 1: one LDS buffer, two barriers per K step.  ST = 2: two LDS
+// buffers; tile t+1 is written to the idle buffer after tile t's MFMAs were
+// issued, one barrier per K step.  A K step of BK = 64 (one buffer) doubles
+// the MFMA work that covers the HBM latency of the next step's loads, which
+// the register budget beside a 4 x 4 wave tile allows only once.
+//
+// Blocks are renumbered so that each of the 8 XCDs (which receive blocks
+// round-robin) works on a contiguous range of tiles, walked in groups of
+// BIG_GROUP m-tiles that sweep n together: blocks resident at the same time
+// on one XCD share A and B panels in its L2.
+//
+// FULL (chosen at launch: M, N multiples of the block tile and K of the K
+// step, so every tile is whole) drops the bounds tests from the loads: a
+// predicated load merges its value after a branch, and the compiler then
+// waits for every load before issuing the next, which serialises the HBM
+// latency of a whole K step.
+// LDS row of a tile with BK complex k: 2 BK halves and a 16 B pad, so that
+// the rows read by one fragment load start in distinct bank groups
+template <int BK> struct BigK {
+  static constexpr int LDK = 2 * BK + 8;   // halves per LDS row
+  static constexpr int CPR = BK / 4;       // 16 B chunks per row
+};
+constexpr int BIG_GROUP = 8;
 
-__device__ __forceinline__ f16x8 bprime_frag(uint4 raw, int parity) {
+// B' fragment from 4 complex values (re, im halves per 32-bit word): for
+// even rows n' the word becomes (re, -im), for odd rows (im, re).  Done with
+// one byte permutation and one xor per word, the selector and sign mask
+// chosen per lane once (a per-lane ternary here compiles to branches).
+struct BPrime {
+  uint32_t sel, xm;
+  __device__ __forceinline__ explicit BPrime(int parity)
+      : sel(parity ? 0x01000302u : 0x03020100u), xm(parity ? 0u : 0x80000000u) {}
+};
+
+__device__ __forceinline__ f16x8 bprime_frag(uint4 raw, const BPrime& bp) {
   uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    w[i] = parity ? ((w[i] >> 16) | (w[i] << 16)) : (w[i] ^ 0x80000000u);
+  for (int i = 0; i < 4; ++i) w[i] = __builtin_amdgcn_perm(w[i], w[i], bp.sel) ^ bp.xm;
   f16x8 r;
   __builtin_memcpy(&r, w, 16);
   return r;
@@ -449,22 +489,35 @@ template <int WM, int WN> struct BigTile {
   static constexpr int BN = 32 * WN;   // complex n per block
 };
 
-template <typename TO, int WM, int WN, int MINB>
+__device__ __forceinline__ void big_tile_of(int64_t bid, int64_t nblk, int64_t mt, int64_t nt, int64_t& z,
+                                            int64_t& tm, int64_t& tn) {
+  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  const int64_t per_z = mt * nt;
+  z = bid / per_z;
+  const int64_t r = bid - z * per_z;
+  const int64_t per_group = int64_t(BIG_GROUP) * nt;
+  const int64_t g = r / per_group, rg = r - g * per_group;
+  const int64_t first = g * BIG_GROUP;
+  const int64_t gsz = mt - first < BIG_GROUP ? mt - first : BIG_GROUP;
+  tm = first + rg % gsz;
+  tn = rg / gsz;
+}
+
+template <typename TO, int WM, int WN, int MINB, int ST, int BK, bool FULL>
 __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
   constexpr int BM = BigTile<WM, WN>::BM, BN = BigTile<WM, WN>::BN;
-  constexpr int NA = BM * 8 / 256, NB = BN * 8 / 256;   // 16 B chunks per thread
-  __shared__ __attribute__((aligned(16))) _Float16 sA[BM * BG_LDK];
-  __shared__ __attribute__((aligned(16))) _Float16 sB[BN * BG_LDK];
+  constexpr int BG_BK = BK, BG_LDK = BigK<BK>::LDK, CPR = BigK<BK>::CPR;
+  constexpr int NA = BM * CPR / 256, NB = BN * CPR / 256;   // 16 B chunks per thread
+  constexpr int NBUF = ST >= 2 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) _Float16 sA[NBUF][BM * BG_LDK];
+  __shared__ __attribute__((aligned(16))) _Float16 sB[NBUF][BN * BG_LDK];
   __shared__ int64_t cmT[BM];
   __shared__ int64_t cnT[BN];
 
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
   const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN;
-  int64_t bid = blockIdx.x;
-  const int64_t tn = bid % nt;
-  bid /= nt;
-  const int64_t tm = bid % mt;
-  const int64_t z = bid / mt;
+  int64_t z, tm, tn;
+  big_tile_of(blockIdx.x, gridDim.x, mt, nt, z, tm, tn);
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -476,36 +529,6 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
   const _Float16* Ab = static_cast<const _Float16*>(a.A) + 2 * ((a.offA ? a.offA[z] : z * M * K) + m0 * K);
   const _Float16* Bb = static_cast<const _Float16*>(a.B) + 2 * ((a.offB ? a.offB[z] : z * N * K) + n0 * K);
 
-  // one 16 B chunk = 4 complex; a tile row of 32 complex = 8 chunks
-  uint4 ra[NA], rb[NB];
-  auto fetch = [&](const _Float16* base, int valid, int row, int ch, int64_t k0) -> uint4 {
-    const int64_t kc = k0 + 4 * ch;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (row < valid) {
-      const _Float16* p = base + 2 * (int64_t(row) * K + kc);
-      if (kc + 4 <= K) {
-        v = *reinterpret_cast<const uint4*>(p);
-      } else if (kc < K) {
-        uint32_t t[4] = {0, 0, 0, 0};
-        for (int e = 0; e < 4 && kc + e < K; ++e) t[e] = reinterpret_cast<const uint32_t*>(p)[e];
-        v = make_uint4(t[0], t[1], t[2], t[3]);
-      }
-    }
-    return v;
-  };
-  auto load = [&](int64_t k0) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int c = tid + 256 * i;
-      ra[i] = fetch(Ab, validM, c >> 3, c & 7, k0);
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int c = tid + 256 * i;
-      rb[i] = fetch(Bb, validN, c >> 3, c & 7, k0);
-    }
-  };
-
   f32x16 acc[WN][WM];
 #pragma unroll
   for (int i = 0; i < WN; ++i)
@@ -514,40 +537,109 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-  load(0);
-  for (int64_t k0 = 0; k0 < K; k0 += BG_BK) {
+  // one 16 B chunk = 4 complex; a tile row of BK complex = CPR chunks
+  {
+    auto fetch = [&](const _Float16* base, int valid, int row, int ch, int64_t k0) -> uint4 {
+      const int64_t kc = k0 + 4 * ch;
+      if constexpr (FULL) {
+        (void)valid;
+        return *reinterpret_cast<const uint4*>(base + 2 * (int64_t(row) * K + kc));
+      } else {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (row < valid) {
+          const _Float16* p = base + 2 * (int64_t(row) * K + kc);
+          if (kc + 4 <= K) {
+            v = *reinterpret_cast<const uint4*>(p);
+          } else if (kc < K) {
+            uint32_t t[4] = {0, 0, 0, 0};
+            for (int e = 0; e < 4 && kc + e < K; ++e) t[e] = reinterpret_cast<const uint32_t*>(p)[e];
+            v = make_uint4(t[0], t[1], t[2], t[3]);
+          }
+        }
+        return v;
+      }
+    };
+    auto load = [&](uint4 (&ra)[NA], uint4 (&rb)[NB], int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int c = tid + 256 * i;
-      *reinterpret_cast<uint4*>(&sA[(c >> 3) * BG_LDK + 8 * (c & 7)]) = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int c = tid + 256 * i;
-      *reinterpret_cast<uint4*>(&sB[(c >> 3) * BG_LDK + 8 * (c & 7)]) = rb[i];
-    }
-    __syncthreads();
-    if (k0 + BG_BK < K) load(k0 + BG_BK);
-#pragma unroll
-    for (int kk = 0; kk < BG_BK; kk += 8) {
-      const int koff = 2 * (kk + 4 * (lane >> 5));   // halves
-      f16x8 af[WM], bf[WN];
-#pragma unroll
-      for (int bm = 0; bm < WM; ++bm)
-        af[bm] = *reinterpret_cast<const f16x8*>(&sA[(wm * 32 * WM + bm * 32 + (lane & 31)) * BG_LDK + koff]);
-#pragma unroll
-      for (int bn = 0; bn < WN; ++bn) {
-        const int np = wn * 32 * WN + bn * 32 + (lane & 31);
-        uint4 raw = *reinterpret_cast<const uint4*>(&sB[(np >> 1) * BG_LDK + koff]);
-        bf[bn] = bprime_frag(raw, np & 1);
+      for (int i = 0; i < NA; ++i) {
+        const int c = tid + 256 * i;
+        ra[i] = fetch(Ab, validM, c / CPR, c % CPR, k0);
       }
 #pragma unroll
-      for (int bn = 0; bn < WN; ++bn)
+      for (int i = 0; i < NB; ++i) {
+        const int c = tid + 256 * i;
+        rb[i] = fetch(Bb, validN, c / CPR, c % CPR, k0);
+      }
+    };
+    auto store = [&](const uint4 (&ra)[NA], const uint4 (&rb)[NB], int buf) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int c = tid + 256 * i;
+        *reinterpret_cast<uint4*>(&sA[buf][(c / CPR) * BG_LDK + 8 * (c % CPR)]) = ra[i];
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int c = tid + 256 * i;
+        *reinterpret_cast<uint4*>(&sB[buf][(c / CPR) * BG_LDK + 8 * (c % CPR)]) = rb[i];
+      }
+    };
+    const BPrime bp(lane & 1);   // parity of the B' row n' of this lane
+    // fragments of k step kk+1 are read from LDS while the MFMAs of step kk
+    // run; scheduling barriers keep the compiler from hoisting the reads of
+    // every step at once (which runs out of registers beside the prefetch)
+    auto compute = [&](int buf) {
+      const _Float16* cA = sA[buf];
+      const _Float16* cB = sB[buf];
+      f16x8 af[2][WM], bf[2][WN];
+      auto read = [&](int kk, int slot) {
+        const int koff = 2 * (kk + 4 * (lane >> 5));   // halves
 #pragma unroll
         for (int bm = 0; bm < WM; ++bm)
-          acc[bn][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[bn], af[bm], acc[bn][bm], 0, 0, 0);
+          af[slot][bm] = *reinterpret_cast<const f16x8*>(&cA[(wm * 32 * WM + bm * 32 + (lane & 31)) * BG_LDK + koff]);
+#pragma unroll
+        for (int bn = 0; bn < WN; ++bn) {
+          const int np = wn * 32 * WN + bn * 32 + (lane & 31);
+          uint4 raw = *reinterpret_cast<const uint4*>(&cB[(np >> 1) * BG_LDK + koff]);
+          bf[slot][bn] = bprime_frag(raw, bp);
+        }
+      };
+      read(0, 0);
+#pragma unroll
+      for (int kk = 0; kk < BG_BK; kk += 8) {
+        const int cur = (kk >> 3) & 1;
+        if (kk + 8 < BG_BK) read(kk + 8, cur ^ 1);
+#pragma unroll
+        for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+          for (int bm = 0; bm < WM; ++bm)
+            acc[bn][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[cur][bn], af[cur][bm], acc[bn][bm], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    const int64_t T = (K + BG_BK - 1) / BG_BK;
+    uint4 ra0[NA], rb0[NB];
+    if constexpr (ST == 2) {
+      load(ra0, rb0, 0);
+      store(ra0, rb0, 0);
+      __syncthreads();
+      for (int64_t t = 0; t < T; ++t) {
+        const int cur = int(t & 1);
+        if (t + 1 < T) load(ra0, rb0, (t + 1) * BG_BK);
+        compute(cur);
+        // the other buffer was last read before the previous barrier
+        if (t + 1 < T) store(ra0, rb0, cur ^ 1);
+        __syncthreads();
+      }
+    } else {
+      load(ra0, rb0, 0);
+      for (int64_t t = 0; t < T; ++t) {
+        store(ra0, rb0, 0);
+        __syncthreads();
+        if (t + 1 < T) load(ra0, rb0, (t + 1) * BG_BK);
+        compute(0);
+        __syncthreads();
+      }
     }
-    __syncthreads();
   }
 
   TO* C = static_cast<TO*>(a.C);
@@ -573,160 +665,135 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
   block_amax_sat(lmax, lsat, a.amax, a.sat);
 }
 
-// ------------------------------------ MFMA, pipelined f16 tile (LDS ping-pong)
-// Same operand handling as gett_mfma_big with the 4 x 4 wave layout (block
-// tile 256 m x 128 complex n x 32 complex k), but two LDS buffers: while the
-// MFMAs consume tile t from one buffer, tile t+1 is fetched from HBM into
-// registers and written to the other buffer afterwards, so each K step needs
-// one barrier instead of two and the LDS writes overlap the matrix cores.
-// The block index is remapped so that each of the 8 XCDs (which receive
-// blocks round-robin) works on a contiguous range of tiles, and within it
-// tiles run in groups of DB_GROUP m-tiles that sweep n together, so
-// concurrently resident blocks share A and B panels in their XCD's L2.
-constexpr int DB_WM = 4, DB_WN = 4, DB_GROUP = 8;
-constexpr int DB_BM = 64 * DB_WM, DB_BN = 32 * DB_WN;
-
-__device__ __forceinline__ void db_tile_of(int64_t bid, int64_t nblk, int64_t mt, int64_t nt, int64_t& z,
-                                           int64_t& tm, int64_t& tn) {
-  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
-  const int64_t per_z = mt * nt;
-  z = bid / per_z;
-  const int64_t r = bid - z * per_z;
-  const int64_t per_group = int64_t(DB_GROUP) * nt;
-  const int64_t g = r / per_group, rg = r - g * per_group;
-  const int64_t first = g * DB_GROUP;
-  const int64_t gsz = mt - first < DB_GROUP ? mt - first : DB_GROUP;
-  tm = first + rg % gsz;
-  tn = rg / gsz;
-}
-
-template <typename TO>
-__global__ void __launch_bounds__(256, 1) gett_mfma_db(GettArgs a) {
-  constexpr int BM = DB_BM, BN = DB_BN;
-  constexpr int NA = BM * 8 / 256, NB = BN * 8 / 256;   // 16 B chunks per thread
-  __shared__ __attribute__((aligned(16))) _Float16 sA[2][BM * BG_LDK];
-  __shared__ __attribute__((aligned(16))) _Float16 sB[2][BN * BG_LDK];
-  __shared__ int64_t cmT[BM];
-  __shared__ int64_t cnT[BN];
-
-  const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
-  const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN;
-  int64_t z, tm, tn;
-  db_tile_of(blockIdx.x, gridDim.x, mt, nt, z, tm, tn);
-  const int64_t m0 = tm * BM, n0 = tn * BN;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w & 1, wn = w >> 1;
-  const int validM = int(M - m0 < BM ? M - m0 : BM);
-  const int validN = int(N - n0 < BN ? N - n0 : BN);
-  for (int i = tid; i < BM; i += 256) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
-  for (int i = tid; i < BN; i += 256) cnT[i] = scatter_bits(n0 + i, a.cn, a.nn);
-  const int64_t czv = scatter_bits(z, a.cz, a.nz);
-  const _Float16* Ab = static_cast<const _Float16*>(a.A) + 2 * ((a.offA ? a.offA[z] : z * M * K) + m0 * K);
-  const _Float16* Bb = static_cast<const _Float16*>(a.B) + 2 * ((a.offB ? a.offB[z] : z * N * K) + n0 * K);
-
-  uint4 ra[NA], rb[NB];
-  auto fetch = [&](const _Float16* base, int valid, int row, int ch, int64_t k0) -> uint4 {
-    const int64_t kc = k0 + 4 * ch;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (row < valid) {
-      const _Float16* p = base + 2 * (int64_t(row) * K + kc);
-      if (kc + 4 <= K) {
-        v = *reinterpret_cast<const uint4*>(p);
-      } else if (kc < K) {
-        uint32_t t[4] = {0, 0, 0, 0};
-        for (int e = 0; e < 4 && kc + e < K; ++e) t[e] = reinterpret_cast<const uint32_t*>(p)[e];
-        v = make_uint4(t[0], t[1], t[2], t[3]);
-      }
-    }
-    return v;
-  };
-  auto load = [&](int64_t k0) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int c = tid + 256 * i;
-      ra[i] = fetch(Ab, validM, c >> 3, c & 7, k0);
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int c = tid + 256 * i;
-      rb[i] = fetch(Bb, validN, c >> 3, c & 7, k0);
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int c = tid + 256 * i;
-      *reinterpret_cast<uint4*>(&sA[buf][(c >> 3) * BG_LDK + 8 * (c & 7)]) = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int c = tid + 256 * i;
-      *reinterpret_cast<uint4*>(&sB[buf][(c >> 3) * BG_LDK + 8 * (c & 7)]) = rb[i];
-    }
-  };
-
-  f32x16 acc[DB_WN][DB_WM];
-#pragma unroll
-  for (int i = 0; i < DB_WN; ++i)
-#pragma unroll
-    for (int j = 0; j < DB_WM; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-
-  const int64_t T = (K + BG_BK - 1) / BG_BK;
-  load(0);
-  store(0);
+// ------------------------------------------------------------ skinny MFMA
+// Steps with a short side: N <= 16 complex (at most 32 rows of B'),
+// 4 <= K <= 64, complex-half A, M >= 32 GPW.  Each wave multiplies 32 rows of
+// A at a time by the whole of B', which it holds in registers (built once per
+// wave), with MFMA 32x32x16 and no LDS.  A is streamed from HBM once and C
+// written once, so the step is bound by HBM rather than by the vector ALU
+// rate of the one-row-per-thread kernels.  A complex64 B is split into a
+// high and a low half (two MFMAs per k step), which keeps its rounding at
+// about 2^-22 relative.  A wave takes GPW consecutive 32-row groups, all
+// inside one batch entry z, and issues all of their loads before its MFMAs.
+template <typename TB, typename TO, int KC, int GPW>
+__global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) {
+  constexpr int S = KC >= 8 ? KC / 8 : 1;   // k steps of 16 reals
+  constexpr bool SPLIT = std::is_same<TB, float>::value;
+  __shared__ int64_t cnT[16];
+  const int64_t M = int64_t(1) << a.nm;
+  const int N = 1 << a.nn;
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x < N) cnT[threadIdx.x] = scatter_bits(threadIdx.x, a.cn, a.nn);
   __syncthreads();
-  for (int64_t t = 0; t < T; ++t) {
-    const int cur = int(t & 1);
-    if (t + 1 < T) load((t + 1) * BG_BK);
-    const _Float16* cA = sA[cur];
-    const _Float16* cB = sB[cur];
+  const int64_t wave = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (wave >= n_waves) return;
+  const int64_t row0 = wave * (32 * GPW);          // first row (z, m) of this wave
+  const int64_t z = row0 >> a.nm;
+  const int64_t m0 = row0 & (M - 1);
+  const int kq = 4 * (lane >> 5);                  // complex k offset of this lane in a step
+
+  // B' fragments: lane row n' = lane % 32, n = n' / 2
+  const BPrime bp(lane & 1);
+  const int n = (lane & 31) >> 1;
+  const int64_t bz = a.offB ? a.offB[z] : z * int64_t(N) * KC;
+  f16x8 bh[S], bl[S];
 #pragma unroll
-    for (int kk = 0; kk < BG_BK; kk += 8) {
-      const int koff = 2 * (kk + 4 * (lane >> 5));   // halves
-      f16x8 af[DB_WM], bf[DB_WN];
+  for (int st = 0; st < S; ++st) {
+    const int kc = st * 8 + kq;
+    uint4 hi = make_uint4(0, 0, 0, 0), lo = make_uint4(0, 0, 0, 0);
+    if (n < N && kc < KC) {
+      if constexpr (SPLIT) {
+        const float* p = static_cast<const float*>(a.B) + 2 * (bz + int64_t(n) * KC + kc);
+        const float4 v0 = reinterpret_cast<const float4*>(p)[0];
+        const float4 v1 = reinterpret_cast<const float4*>(p)[1];
+        const float x[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        uint32_t wh[4], wl[4];
 #pragma unroll
-      for (int bm = 0; bm < DB_WM; ++bm)
-        af[bm] = *reinterpret_cast<const f16x8*>(&cA[(wm * 32 * DB_WM + bm * 32 + (lane & 31)) * BG_LDK + koff]);
-#pragma unroll
-      for (int bn = 0; bn < DB_WN; ++bn) {
-        const int np = wn * 32 * DB_WN + bn * 32 + (lane & 31);
-        uint4 raw = *reinterpret_cast<const uint4*>(&cB[(np >> 1) * BG_LDK + koff]);
-        bf[bn] = bprime_frag(raw, np & 1);
+        for (int e = 0; e < 4; ++e) {
+          f16x2 h, l;
+          h[0] = (_Float16)x[2 * e];
+          h[1] = (_Float16)x[2 * e + 1];
+          l[0] = (_Float16)(x[2 * e] - float(h[0]));
+          l[1] = (_Float16)(x[2 * e + 1] - float(h[1]));
+          __builtin_memcpy(&wh[e], &h, 4);
+          __builtin_memcpy(&wl[e], &l, 4);
+        }
+        hi = make_uint4(wh[0], wh[1], wh[2], wh[3]);
+        lo = make_uint4(wl[0], wl[1], wl[2], wl[3]);
+      } else {
+        hi = *reinterpret_cast<const uint4*>(static_cast<const _Float16*>(a.B) + 2 * (bz + int64_t(n) * KC + kc));
       }
-#pragma unroll
-      for (int bn = 0; bn < DB_WN; ++bn)
-#pragma unroll
-        for (int bm = 0; bm < DB_WM; ++bm)
-          acc[bn][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[bn], af[bm], acc[bn][bm], 0, 0, 0);
     }
-    // the other buffer was last read before the previous barrier
-    if (t + 1 < T) store(cur ^ 1);
-    __syncthreads();
+    bh[st] = bprime_frag(hi, bp);
+    if constexpr (SPLIT) bl[st] = bprime_frag(lo, bp);
   }
 
+  const _Float16* A = static_cast<const _Float16*>(a.A) + 2 * (a.offA ? a.offA[z] : z * M * KC);
+  f16x8 af[GPW][S];
+#pragma unroll
+  for (int g = 0; g < GPW; ++g)
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      const int kc = st * 8 + kq;
+      const int64_t m = m0 + g * 32 + (lane & 31);
+      if (kc < KC) {
+        af[g][st] = *reinterpret_cast<const f16x8*>(A + 2 * (m * KC + kc));
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) af[g][st][e] = (_Float16)0.0f;
+      }
+    }
+
   TO* C = static_cast<TO*>(a.C);
+  const int64_t czv = scatter_bits(z, a.cz, a.nz);
   float lmax = 0.0f;
   unsigned lsat = 0;
 #pragma unroll
-  for (int bn = 0; bn < DB_WN; ++bn)
+  for (int g = 0; g < GPW; ++g) {
+    f32x16 acc;
 #pragma unroll
-    for (int bm = 0; bm < DB_WM; ++bm) {
-      const int ml = wm * 32 * DB_WM + bm * 32 + (lane & 31);
-      if (ml >= validM) continue;
-      const int64_t cb = czv + cmT[ml];
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
 #pragma unroll
-      for (int v = 0; v < 16; v += 2) {
-        const int np = wn * 32 * DB_WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int nl = np >> 1;
-        if (nl >= validN) continue;
-        const float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
-        lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
-        if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
-      }
+    for (int st = 0; st < S; ++st) {
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[st], af[g][st], acc, 0, 0, 0);
+      if constexpr (SPLIT) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[st], af[g][st], acc, 0, 0, 0);
     }
+    const int64_t m = m0 + g * 32 + (lane & 31);
+    const int64_t cb = czv + scatter_bits(m, a.cm, a.nm);
+#pragma unroll
+    for (int v = 0; v < 16; v += 2) {
+      const int nl = (8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1;
+      if (nl >= N) continue;
+      const float re = acc[v] * a.scale, im = acc[v + 1] * a.scale;
+      lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+      if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
+    }
+  }
   block_amax_sat(lmax, lsat, a.amax, a.sat);
+}
+
+template <typename TB, typename TO, int KC>
+static hipError_t launch_skinny_k(const GettArgs& a, hipStream_t s) {
+  constexpr int GPW = KC >= 64 ? 2 : 4;
+  const int64_t rows = (int64_t(1) << a.nz) << a.nm;
+  if (((int64_t(1) << a.nm) % (32 * GPW)) != 0) return hipErrorInvalidValue;
+  const int64_t n_waves = rows / (32 * GPW);
+  const int64_t blocks = (n_waves + 3) / 4;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW>), dim3(unsigned(blocks)), dim3(256), 0, s, a, n_waves);
+  return hipGetLastError();
+}
+
+template <typename TB, typename TO>
+static hipError_t launch_skinny(const GettArgs& a, hipStream_t s) {
+  switch (a.nk) {
+    case 2: return launch_skinny_k<TB, TO, 4>(a, s);
+    case 3: return launch_skinny_k<TB, TO, 8>(a, s);
+    case 4: return launch_skinny_k<TB, TO, 16>(a, s);
+    case 5: return launch_skinny_k<TB, TO, 32>(a, s);
+    case 6: return launch_skinny_k<TB, TO, 64>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ------------------------------------------------------------ launchers
@@ -737,8 +804,9 @@ bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
   if (kernel == K_MFMA) return nm >= 5 && nn >= 4;
   if (kernel == K_MFMA_BIG) return in_dt == 1 && nm >= 7 && nn >= 5;
   if (kernel == K_MFMA_WIDE) return in_dt == 1 && nm >= 7 && nn >= 6;
-  if (kernel == K_MFMA_DB) return in_dt == 1 && nm >= 7 && nn >= 6;
+  if (kernel == K_MFMA_DB || kernel == K_MFMA_DEEP) return in_dt == 1 && nm >= 7 && nn >= 6;
   if (kernel == K_NARROW) return nm >= 8 && nk <= 6 && nn <= 8 && nn + nk <= 8;
+  if (kernel == K_SKINNY) return in_dt == 1 && nn <= 4 && nk >= 2 && nk <= 6 && nm >= (nk == 6 ? 6 : 7);
   return false;
 }
 
@@ -751,10 +819,27 @@ static hipError_t launch_thin(const GettArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename TO, int WM, int WN, int MINB, int ST, int BK>
+static hipError_t launch_big(const GettArgs& a, hipStream_t s) {
+  using T = BigTile<WM, WN>;
+  const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
+  const int64_t blocks = (int64_t(1) << a.nz) * ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const bool full = M % T::BM == 0 && N % T::BN == 0 && K % BK == 0;
+  if (full)
+    hipLaunchKernelGGL((gett_mfma_big<TO, WM, WN, MINB, ST, BK, true>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((gett_mfma_big<TO, WM, WN, MINB, ST, BK, false>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename TI, typename TO>
 static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
   if (kernel == K_THIN) return launch_thin<TI, TI, TO>(a, s);
   if (kernel == K_NARROW) return launch_narrow<TI, TI, TO>(a, s);
+  if constexpr (std::is_same<TI, _Float16>::value) {
+    if (kernel == K_SKINNY) return launch_skinny<_Float16, TO>(a, s);
+  }
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn;
   if (kernel == K_MFMA) {
     const int64_t blocks = (int64_t(1) << a.nz) * ((M + MF_BM - 1) / MF_BM) * ((N + MF_BN - 1) / MF_BN);
@@ -762,21 +847,10 @@ static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((gett_mfma<TI, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
   } else {
     if constexpr (std::is_same<TI, _Float16>::value) {
-      if (kernel == K_MFMA_BIG) {
-        using T = BigTile<4, 2>;
-        const int64_t blocks = (int64_t(1) << a.nz) * ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
-        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((gett_mfma_big<TO, 4, 2, 2>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
-      } else if (kernel == K_MFMA_DB) {
-        const int64_t blocks = (int64_t(1) << a.nz) * ((M + DB_BM - 1) / DB_BM) * ((N + DB_BN - 1) / DB_BN);
-        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((gett_mfma_db<TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
-      } else {
-        using T = BigTile<4, 4>;
-        const int64_t blocks = (int64_t(1) << a.nz) * ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
-        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((gett_mfma_big<TO, 4, 4, 1>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
-      }
+      if (kernel == K_MFMA_BIG) return launch_big<TO, 4, 2, 2, 1, 32>(a, s);
+      if (kernel == K_MFMA_WIDE) return launch_big<TO, 4, 4, 1, 1, 32>(a, s);
+      if (kernel == K_MFMA_DB) return launch_big<TO, 4, 4, 1, 2, 32>(a, s);
+      return launch_big<TO, 4, 4, 1, 1, 64>(a, s);
     } else {
       return hipErrorInvalidValue;
     }
@@ -790,6 +864,8 @@ hipError_t launch_gett(int kernel, int a_dt, int b_dt, int out_dt, const GettArg
     if (a_dt != 1 || b_dt != 0) return hipErrorInvalidValue;
     if (kernel == K_NARROW && kernel_applicable(K_NARROW, 1, a.nz, a.nm, a.nn, a.nk))
       return out_dt ? launch_narrow<_Float16, float, _Float16>(a, s) : launch_narrow<_Float16, float, float>(a, s);
+    if (kernel == K_SKINNY && kernel_applicable(K_SKINNY, 1, a.nz, a.nm, a.nn, a.nk))
+      return out_dt ? launch_skinny<float, _Float16>(a, s) : launch_skinny<float, float>(a, s);
     return out_dt ? launch_thin<_Float16, float, _Float16>(a, s) : launch_thin<_Float16, float, float>(a, s);
   }
   const int in_dt = a_dt;

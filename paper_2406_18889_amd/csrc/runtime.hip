@@ -92,10 +92,16 @@ struct lf_plan {
   hipStream_t graph_stream = nullptr;
   int graph_slices = 0;
   hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
+  // live timing of one kernel's launches in stream-mode contractions
+  int time_kernel = -1;
+  std::vector<hipEvent_t> tev;       // event pool, two per timed launch
+  std::vector<int> tev_step;         // step of each pair in use
+  size_t tev_used = 0;               // pairs in use
   ~lf_plan() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (hipEvent_t e : tev) (void)hipEventDestroy(e);
   }
 };
 
@@ -366,13 +372,36 @@ lf_status calibrate(lf_plan* P, int64_t sigma, hipStream_t stream) {
   return LF_OK;
 }
 
+// grow the event pool so that `pairs` timed launches fit
+lf_status reserve_events(lf_plan* P, size_t pairs) {
+  while (P->tev.size() < 2 * pairs) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    P->tev.push_back(e);
+  }
+  if (P->tev_step.size() < pairs) P->tev_step.resize(pairs);
+  return LF_OK;
+}
+
+// timed: bracket the launches of kernel P->time_kernel with events on the
+// launch stream (stream mode only: events are not recorded into graphs)
 lf_status run_slice(lf_plan* P, const int64_t* sigma_dev, int64_t sigma, double* out,
-                    hipStream_t stream) {
+                    hipStream_t stream, bool timed = false) {
   HIPCHK(launch_instantiate(reinterpret_cast<const SliceCopy*>(P->ws + P->off_copies_tab),
                             int(P->copies.size()), P->copy_max_n, P->ws, sigma_dev, sigma, stream));
   for (int s : P->variant_steps) {
+    const bool tk = timed && P->hp.steps[s].kernel == P->time_kernel;
+    size_t pair = 0;
+    if (tk) {
+      pair = P->tev_used++;
+      lf_status r = reserve_events(P, P->tev_used);
+      if (r) return r;
+      P->tev_step[pair] = s;
+      HIPCHK(hipEventRecord(P->tev[2 * pair], stream));
+    }
     lf_status r = run_step(P, s, stream);
     if (r) return r;
+    if (tk) HIPCHK(hipEventRecord(P->tev[2 * pair + 1], stream));
   }
   const int r = P->root;
   const int64_t n = P->net.n_batch << P->net.open_qubits.size();
@@ -686,7 +715,7 @@ static lf_status autotune(lf_plan* P, int64_t sigma, hipStream_t st) {
         any_tile |= k != K_NARROW && kernel_applicable(k, stp.dtype, stp.nz, stp.nm, stp.nn, stp.nk);
       for (int k = 0; k < K_COUNT && r == LF_OK; ++k) {
         if (!kernel_applicable(k, stp.dtype, stp.nz, stp.nm, stp.nn, stp.nk)) continue;
-        if (mixed && k != K_THIN && k != K_NARROW) continue;
+        if (mixed && k != K_THIN && k != K_NARROW && k != K_SKINNY) continue;
         // the streaming kernel is a candidate only for a narrow side
         if (k == K_THIN && any_tile && stp.nn + stp.nk > 10) continue;
         stp.kernel = k;
@@ -792,7 +821,7 @@ lf_status lf_contract_slices(lf_plan* P, int64_t s0, int64_t s1, void* out_amps,
     if (r) return r;
   } else {
     for (int64_t s = s0; s < s1; ++s) {
-      r = run_slice(P, nullptr, s, out, st);
+      r = run_slice(P, nullptr, s, out, st, P->time_kernel >= 0);
       if (r) return r;
     }
   }
@@ -1011,6 +1040,37 @@ lf_status lf_profile_steps(lf_plan* P, int32_t reps, double* out_ms, void* strea
   return r;
 }
 
+lf_status lf_plan_time_kernel(lf_plan* P, int32_t kernel, int64_t reserve_launches) {
+  if (!P) return fail(LF_INVALID_ARGUMENT, "plan is NULL");
+  if (kernel < -1 || kernel >= lf::K_COUNT) return fail(LF_INVALID_ARGUMENT, "kernel id");
+  if (reserve_launches < 0 || reserve_launches > (int64_t(1) << 20))
+    return fail(LF_INVALID_ARGUMENT, "reserve_launches outside [0, 2^20]");
+  P->time_kernel = kernel;
+  P->tev_used = 0;
+  return reserve_events(P, size_t(reserve_launches));
+}
+
+lf_status lf_plan_kernel_times(lf_plan* P, double* total_ms, int64_t* launches, double* per_step_ms,
+                               int64_t* per_step_launches) {
+  if (!P || !total_ms || !launches) return fail(LF_INVALID_ARGUMENT, "NULL pointer");
+  const size_t ns = P->hp.steps.size();
+  if (per_step_ms) std::fill(per_step_ms, per_step_ms + ns, 0.0);
+  if (per_step_launches) std::fill(per_step_launches, per_step_launches + ns, int64_t(0));
+  *total_ms = 0.0;
+  *launches = int64_t(P->tev_used);
+  if (P->tev_used) HIPCHK(hipEventSynchronize(P->tev[2 * P->tev_used - 1]));
+  for (size_t i = 0; i < P->tev_used; ++i) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, P->tev[2 * i], P->tev[2 * i + 1]));
+    *total_ms += ms;
+    const int s = P->tev_step[i];
+    if (per_step_ms) per_step_ms[s] += ms;
+    if (per_step_launches) per_step_launches[s] += 1;
+  }
+  P->tev_used = 0;
+  return LF_OK;
+}
+
 lf_status lf_autotune_save(const char* path) {
   if (!path) return fail(LF_INVALID_ARGUMENT, "path is NULL");
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1040,12 +1100,14 @@ lf_status lf_autotune_load(const char* path) {
   return LF_OK;
 }
 
-lf_status lf_contract_pair(int32_t dtype_in, int32_t dtype_out, int32_t kernel, const void* A,
-                           const void* B, void* C, int32_t nz, int32_t nm, int32_t nn, int32_t nk,
-                           const int64_t* c_strides, float scale, void* stream) {
+lf_status lf_contract_pair(int32_t dtype_a, int32_t dtype_b, int32_t dtype_out, int32_t kernel,
+                           const void* A, const void* B, void* C, int32_t nz, int32_t nm, int32_t nn,
+                           int32_t nk, const int64_t* c_strides, float scale, void* stream) {
   if (!A || !B || !C || !c_strides) return fail(LF_INVALID_ARGUMENT, "NULL pointer");
-  if ((dtype_in != 0 && dtype_in != 1) || (dtype_out != 0 && dtype_out != 1))
+  if ((dtype_a != 0 && dtype_a != 1) || (dtype_b != 0 && dtype_b != 1) || (dtype_out != 0 && dtype_out != 1))
     return fail(LF_INVALID_ARGUMENT, "dtype must be LF_C64 or LF_CHALF");
+  if (dtype_a != dtype_b && !(dtype_a == 1 && dtype_b == 0))
+    return fail(LF_INVALID_ARGUMENT, "mixed operands: only a complex-half A with a complex64 B");
   if (nz < 0 || nm < 0 || nn < 0 || nk < 0 || nz > lf::MAXZ || nm > lf::MAXMN || nn > lf::MAXMN ||
       nk > 40 || nz + nm + nk > 40 || nz + nn + nk > 40)
     return fail(LF_INVALID_ARGUMENT, "sizes out of range");
@@ -1065,8 +1127,8 @@ lf_status lf_contract_pair(int32_t dtype_in, int32_t dtype_out, int32_t kernel, 
   for (int i = 0; i < nn; ++i) a.cn[i] = c_strides[nz + nm + i];
   a.scale = scale;
   if (kernel < 0)
-    kernel = lf::kernel_applicable(lf::K_MFMA, dtype_in, nz, nm, nn, nk) && nk >= 2 ? lf::K_MFMA : lf::K_THIN;
-  HIPCHK(lf::launch_gett(kernel, dtype_in, dtype_in, dtype_out, a, as_stream(stream)));
+    kernel = lf::kernel_applicable(lf::K_MFMA, dtype_a, nz, nm, nn, nk) && nk >= 2 ? lf::K_MFMA : lf::K_THIN;
+  HIPCHK(lf::launch_gett(kernel, dtype_a, dtype_b, dtype_out, a, as_stream(stream)));
   return LF_OK;
 }
 

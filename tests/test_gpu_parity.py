@@ -86,7 +86,7 @@ SHAPES = [
     (0, 10, 2, 2), (0, 3, 1, 0), (2, 6, 5, 3), (0, 8, 7, 6), (3, 7, 6, 5),
     (0, 9, 6, 9), (1, 4, 4, 1), (0, 5, 4, 4), (0, 12, 8, 4), (0, 8, 6, 1), (2, 7, 5, 0),
     (0, 9, 7, 2), (1, 9, 3, 3), (0, 8, 0, 6), (2, 8, 4, 0), (0, 13, 2, 2), (0, 10, 4, 4),
-    (1, 8, 8, 0), (1, 10, 9, 3), (0, 9, 8, 3),
+    (1, 8, 8, 0), (1, 10, 9, 3), (0, 9, 8, 3), (2, 7, 4, 5), (0, 6, 3, 6),
 ]
 
 
@@ -98,8 +98,10 @@ def _applicable(kernel, dt, shape):
         return dt == "chalf" and nm >= 7 and nn >= 5
     if kernel == 3:
         return nm >= 8 and nk <= 6 and nn <= 8 and nn + nk <= 8
-    if kernel in (4, 5):
+    if kernel in (4, 5, 6):
         return dt == "chalf" and nm >= 7 and nn >= 6
+    if kernel == 7:
+        return dt == "chalf" and nn <= 4 and 2 <= nk <= 6 and nm >= (6 if nk == 6 else 7)
     return True
 
 
@@ -127,7 +129,7 @@ def _to_half_pairs(x, e):
     return torch.from_numpy(v.astype(np.float16)).cuda()
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_pair_chalf(lf, kernel, shape):
     nz, nm, nn, nk = shape
@@ -150,6 +152,30 @@ def test_pair_chalf(lf, kernel, shape):
     # inputs exact in both; the only roundings are fp32 accumulation and the
     # final fp16 store
     assert rel_err(got, ref) < 2e-3
+
+
+@pytest.mark.parametrize("kernel", [0, 3, 7])
+@pytest.mark.parametrize("shape", [(0, 10, 2, 2), (1, 9, 3, 3), (0, 10, 4, 4), (2, 7, 4, 5),
+                                   (0, 6, 3, 6), (0, 8, 0, 6), (0, 13, 2, 2)])
+def test_pair_mixed_half_a_c64_b(lf, kernel, shape):
+    """Complex-half A with a complex64 B (the planner keeps small B
+    operands in complex64), complex64 result: B enters the streaming kernels
+    exactly and the MFMA kernel as a high + low half pair."""
+    nz, nm, nn, nk = shape
+    if not _applicable(kernel, "chalf", shape):
+        pytest.skip("kernel variant not applicable to this shape")
+    _say(f"pair mixed kernel={kernel} shape={shape}")
+    A = wl.random_complex((1 << (nz + nm + nk),), seed=31 + sum(shape))
+    B = wl.random_complex((1 << (nz + nn + nk),), seed=32 + sum(shape)).astype(np.complex64)
+    st = _rand_strides(nz, nm, nn, seed=33 + sum(shape))
+    dA = _to_half_pairs(A, 0)
+    dB = torch.from_numpy(B).cuda()
+    dC = torch.zeros(1 << (nz + nm + nn), dtype=torch.complex64, device="cuda")
+    lf.contract_pair(dA, dB, dC, nz, nm, nn, nk, st, 1.0, kernel)
+    torch.cuda.synchronize()
+    Ah = dA.cpu().numpy().astype(np.float64) @ np.array([1, 1j])
+    ref = _scatter(_ref_pair(Ah, B.astype(np.complex128), nz, nm, nn, nk), nz, nm, nn, st)
+    assert rel_err(dC.cpu().numpy(), ref) < C64_TOL
 
 
 def test_pair_half_in_c64_out(lf):
