@@ -135,11 +135,21 @@ def run_mix(args):
     import workloads as wl
 
     circuits, subtasks = wl.mixed_workload()
+    t_start = time.time()
+
+    def say(msg):
+        print(f"[mix512 {time.time() - t_start:6.1f}s] {msg}", file=sys.stderr, flush=True)
 
     def plans_for(dtype):
         ps = [lf.Plan(c["circuit"], c["open_qubits"], c["closed_bits"], max_log2=c["max_log2"],
                       dtype=dtype, search_dtype="chalf", check_overflow=False).bind()
               for c in circuits]
+        say(f"{dtype}: {len(ps)} plans bound")
+        # calibration and kernel tuning of each plan, on scratch accumulators
+        for k, p in enumerate(ps):
+            p.contract(0, 1, p.new_amplitudes())
+            torch.cuda.synchronize()
+            say(f"{dtype}: plan {k} ready ({p.info()['n_steps']} steps)")
         outs = [p.new_amplitudes() for p in ps]
         items = []
         for (k, draw) in subtasks:
@@ -152,14 +162,17 @@ def run_mix(args):
             lf.contract_batch(items, mode)
             for o, c in zip(outs, circuits):
                 lf.postselect_topk(o, 1 << len(c["open_qubits"]), 1)
-        for _ in range(warmup):
+        for i in range(warmup):
             one()
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            say(f"{mode}: warm-up step {i} done")
         t0 = time.perf_counter()
         for _ in range(steps):
             one()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+        dt = (time.perf_counter() - t0) / steps
+        say(f"{mode}: {steps} timed steps, {dt * 1e3:.1f} ms per step")
+        return dt
 
     ps, outs, items = plans_for(args.dtype)
     macs = sum(ps[k].info()["macs_per_slice"] for (k, _) in subtasks)

@@ -77,7 +77,8 @@ typedef struct lf_plan_opts {
   int32_t n_sliced_wires;        /* -1: as many as the cap needs; >= 0: at least this many */
   const int32_t* sliced_wires;   /* optional forced wires, pairs (q, j), bit order; NULL = planner */
   int32_t n_forced;              /* number of pairs in sliced_wires */
-  int32_t cost_model;            /* LF_COST_FLOPMEM or LF_COST_MLP (needs a loaded model) */
+  int32_t cost_model;            /* LF_COST_FLOPMEM or LF_COST_MLP (needs a loaded model):
+                                    the cost that ranks the refined candidates (restarts) */
   int32_t greedy_trials;         /* randomized greedy trees tried */
   int32_t partition_trials;      /* recursive min-cut bisection trees tried */
   int64_t sa_iters;              /* annealing moves over the best tree (0 = none) */
@@ -95,6 +96,12 @@ typedef struct lf_plan_opts {
   int32_t autotune;              /* nonzero: the first contraction times every applicable
                                     kernel variant (tile shape) per step shape and keeps
                                     the fastest; results are shared by the process */
+  int32_t restarts;              /* >= 1: the `restarts` best candidate trees are each
+                                    annealed and sliced to the cap; the ranking cost
+                                    (cost_model: the learned model, else FLOP + memory)
+                                    of the whole sliced network picks one.  The ranking
+                                    cost also chooses the wires to slice; tree moves
+                                    (annealing) always run on FLOP + memory */
 } lf_plan_opts;
 
 typedef struct lf_plan_info {

@@ -49,7 +49,7 @@ class lf_plan_opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("chalf_min_log2", ctypes.c_int32),
                 ("launch_mode", ctypes.c_int32), ("check_overflow", ctypes.c_int32),
                 ("slices_per_graph", ctypes.c_int32), ("search_dtype", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("restarts", ctypes.c_int32)]
 
 
 class lf_batch_item(ctypes.Structure):

@@ -53,7 +53,8 @@ class Plan:
                 partition_trials: int = 64, sa_iters: int = 0,
                  seed: int = 1, chalf_min_log2: int = 16, launch: str = "stream",
                  check_overflow: bool = True, slices_per_graph: int = 8,
-                 search_dtype: Optional[str] = None, autotune: bool = True):
+                 search_dtype: Optional[str] = None, autotune: bool = True,
+                 restarts: int = 1):
         lib = _lib.load()
         self._lib = lib
         self._handle = ctypes.c_void_p()
@@ -82,6 +83,7 @@ class Plan:
         opts.slices_per_graph = slices_per_graph
         opts.search_dtype = -1 if search_dtype is None else DTYPES[search_dtype]
         opts.autotune = 1 if autotune else 0
+        opts.restarts = int(restarts)
         c, arr = _circuit_struct(circuit)
         openq = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         cb = np.ascontiguousarray(self.closed_bits)

@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import json
 import math
 import os
 import time
@@ -270,6 +271,80 @@ def collect(target_steps: int = 50_000, seed: int = 0, reps: int = 2, log=print,
     return np.concatenate(Xs), np.concatenate(ts), np.concatenate(ds)
 
 
+def compare_rankings(model, n_circuits: int = 6, restarts: int = 4, sa_iters: int = 2_000_000,
+                     seed: int = 99, slices: int = 6, log=print):
+    """End-to-end comparison of the two ranking costs, measured runtime as
+    the judge: for seeded 53-qubit, 20-cycle circuits (cap 2^28, 256 closed
+    strings, 10 open qubits, complex-half), plans searched with the same
+    seeds and restarts, the wires to slice and the candidate kept chosen by
+    FLOP + memory or by the network; each plan's slices/s is measured and
+    its whole-network time is n_slices / (slices/s)."""
+    import concurrent.futures as cf
+
+    import torch
+
+    import workloads as wl
+    from .api import Plan
+
+    load_into_planner(model)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    specs = []
+    for _ in range(n_circuits):
+        circ = wl.random_circuit(6, 9, 20, int(rng.integers(1, 1 << 30)), 1, int(rng.integers(1, 1000)))
+        openq = list(range(circ.n_qubits - 10, circ.n_qubits))
+        cb = wl.closed_bitstrings(circ.n_qubits, openq, 256, int(rng.integers(1, 1 << 30)))
+        specs.append((circ, openq, cb))
+
+    def make(args):
+        i, cost = args
+        circ, openq, cb = specs[i]
+        try:
+            return Plan(circ, openq, cb, dtype="chalf", max_log2=28, sa_iters=sa_iters, cost_model=cost,
+                        check_overflow=False, restarts=restarts, seed=1 + i)
+        except Exception as e:  # infeasible
+            return e
+
+    def rate(p):
+        p.bind()
+        a = p.new_amplitudes()
+        p.contract(0, 2, a)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        p.contract(2, 2 + slices, a)
+        torch.cuda.synchronize()
+        return slices / (time.perf_counter() - t)
+
+    runs = []
+    with cf.ThreadPoolExecutor(12) as ex:
+        futs = {(i, c): ex.submit(make, (i, c)) for i in range(n_circuits) for c in ("flopmem", "mlp")}
+        for i in range(n_circuits):
+            pf, pm = futs[(i, "flopmem")].result(), futs[(i, "mlp")].result()
+            if isinstance(pf, Exception) or isinstance(pm, Exception):
+                log(f"circuit {i}: no plan ({pf if isinstance(pf, Exception) else pm})")
+                continue
+            fi, mi = pf.info(), pm.info()
+            same = pf.sliced_wires() == pm.sliced_wires() and fi["macs_per_slice"] == mi["macs_per_slice"]
+            rf = rate(pf)
+            rm = rf if same else rate(pm)
+            tf = fi["n_sliced_wires"] - math.log2(rf)
+            tm = mi["n_sliced_wires"] - math.log2(rm)
+            r = {"circuit": i, "same_choice": bool(same),
+                 "flopmem": {"n_sliced": fi["n_sliced_wires"], "macs_per_slice": fi["macs_per_slice"],
+                             "slices_per_s": rf, "log2_network_seconds": tf},
+                 "mlp": {"n_sliced": mi["n_sliced_wires"], "macs_per_slice": mi["macs_per_slice"],
+                         "slices_per_s": rm, "log2_network_seconds": tm},
+                 "gain_network_time": float(2.0 ** (tf - tm))}
+            log(json.dumps(r))
+            runs.append(r)
+            pf.close()
+            pm.close()
+            torch.cuda.empty_cache()
+    g = [r["gain_network_time"] for r in runs]
+    return {"restarts": restarts, "sa_iters": sa_iters, "circuits": len(runs),
+            "differing_choices": sum(not r["same_choice"] for r in runs),
+            "geomean_gain_network_time": float(np.exp(np.mean(np.log(g)))) if g else None, "runs": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd")
@@ -282,6 +357,11 @@ def main():
     t.add_argument("--data", required=True)
     t.add_argument("--out", default=DEFAULT_MODEL)
     t.add_argument("--epochs", type=int, default=60)
+    c2 = sub.add_parser("compare")
+    c2.add_argument("--model", default=DEFAULT_MODEL)
+    c2.add_argument("--circuits", type=int, default=6)
+    c2.add_argument("--restarts", type=int, default=4)
+    c2.add_argument("--out", required=True)
     args = ap.parse_args()
     if args.cmd == "collect":
         X, y, d = collect(args.steps, args.seed, time_budget=args.budget)
@@ -299,6 +379,12 @@ def main():
         mse = float(np.mean((pred - y[te]) ** 2))
         print(f"test MSE of log seconds: {mse:.4f} on {n_test} held-out steps")
         save(model, args.out)
+    elif args.cmd == "compare":
+        res = compare_rankings(load(args.model), args.circuits, args.restarts,
+                               log=lambda m: print(m, flush=True))
+        with open(args.out, "w") as f:
+            json.dump(res, f)
+        print(json.dumps({k: v for k, v in res.items() if k != "runs"}))
     else:
         ap.print_help()
 

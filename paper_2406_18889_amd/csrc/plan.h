@@ -117,6 +117,7 @@ struct PlanOptions {
   int dtype = 0;               // 0 complex64, 1 complex-half
   int search_dtype = 0;        // arithmetic whose step costs the search minimises
   int chalf_min_log2 = 16;     // tensors at least this large run in half
+  int restarts = 1;            // best candidate trees refined; the ranking cost picks one
   double bytes_per_elem = 8.0;
 };
 
@@ -172,8 +173,10 @@ struct HostPlan {
 
 struct CostFn;  // step cost callback
 
+// rank_cost: cost that chooses among the refined candidates (null: the
+// FLOP + memory cost that drives the search)
 std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& hp,
-                         const CostFn* cost);
+                         const CostFn* rank_cost);
 
 // Step cost used in the search: predicted time units of one step from its
 // bit counts.  The default is FLOP + memory; the MLP model replaces it.

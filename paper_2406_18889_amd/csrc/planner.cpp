@@ -554,9 +554,15 @@ const CostFn& default_cost() {
 }
 
 std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& hp,
-                         const CostFn* cost) {
+                         const CostFn* rank_cost) {
   hp = HostPlan();
-  const CostFn& cf = cost ? *cost : default_cost();
+  // the tree search (candidate ranking, annealing) runs on the FLOP +
+  // memory cost; `rank_cost` (the learned model, when given) ranks complete
+  // alternatives: which wire to slice next (each choice scored over the
+  // whole sliced network), which slices to drop, and which of the refined
+  // candidates to keep
+  const CostFn& cf = default_cost();
+  const CostFn& rank_cf = rank_cost ? *rank_cost : default_cost();
   Ctx C(net);
   const int L = int(net.leaves.size());
   if (L < 2) return "network needs at least two tensors";
@@ -577,9 +583,10 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
   }
   const bool fixed_slices = !opt.forced_slices.empty() || opt.n_sliced == 0;
 
-  // 1. candidate trees, ranked by their cost with the forced slices only
-  Candidate best;
-  best.sl = Bits(C.nidx);
+  // 1. candidate trees, ranked by their cost with the forced slices only;
+  //    the `restarts` best distinct ones are refined
+  const int R = std::max(1, opt.restarts);
+  std::vector<Candidate> top;   // ascending key, at most R
   auto offer = [&](const Tree& t) {
     Candidate c;
     c.sl = forced;
@@ -589,7 +596,14 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
     Score s = score(C, c.tree, c.e, c.sl, int(c.order.size()), cf, opt.search_dtype, opt.chalf_min_log2);
     // over the cap only counts when the slices are fixed by the caller
     c.key = s.total + (fixed_slices && s.max_w > cap ? 1e30 * (s.max_w - cap) : 0);
-    if (c.key < best.key) best = std::move(c);
+    if (!std::isfinite(c.key)) return;
+    for (const Candidate& o : top)
+      if (o.key == c.key) return;   // the same tree found twice
+    if (int(top.size()) == R && c.key >= top.back().key) return;
+    auto at = std::upper_bound(top.begin(), top.end(), c.key,
+                               [](double k, const Candidate& o) { return k < o.key; });
+    top.insert(at, std::move(c));
+    if (int(top.size()) > R) top.pop_back();
   };
   const double alphas[3] = {1.0, 0.5, 0.0};
   const int bws[3] = {net.nb, std::max(0, net.nb / 2), 0};
@@ -622,9 +636,18 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
       offer(t);
     }
   }
-  if (!std::isfinite(best.key)) return "no tree found";
+  if (top.empty()) return "no tree found";
 
-  // 2. anneal the best tree (half of the budget), with the forced slices
+  Candidate best;
+  best.sl = Bits(C.nidx);
+  double best_rank = std::numeric_limits<double>::infinity();
+  std::string first_err;
+  for (int r = 0; r < int(top.size()); ++r) {
+  Candidate cand = std::move(top[r]);
+  const uint64_t rseed = opt.seed + 1000003ULL * uint64_t(r);
+  std::string err = [&]() -> std::string {
+  Candidate& best = cand;
+  // 2. anneal the candidate tree (half of the budget), with the forced slices
   const long sa_half = std::max(0L, opt.sa_iters / 2);
   auto current = [&]() {
     return score(C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.search_dtype,
@@ -634,7 +657,7 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
     int lim = fixed_slices ? std::max(cap, current().max_w) : INT_MAX / 4;
     Annealer an{C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.search_dtype,
                 opt.chalf_min_log2, lim};
-    an.run(sa_half, opt.seed + 101, 0.05, 0.002);
+    an.run(sa_half, rseed + 101, 0.05, 0.002);
     evaluate_sets(C, leaf_idx, best.tree, best.e);
   }
   // 3. slice down to the cap: a few wires at a time, each round followed by
@@ -646,13 +669,13 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
     for (Score sc = current(); sc.max_w > cap; sc = current(), ++rounds) {
       if (int(best.order.size()) >= 62) return "no tree fits the memory cap within 62 sliced wires";
       int target = std::max(cap, sc.max_w - per_round);
-      greedy_slice(C, best.tree, best.e, target, cf, opt.search_dtype, opt.chalf_min_log2, best.sl,
+      greedy_slice(C, best.tree, best.e, target, rank_cf, opt.search_dtype, opt.chalf_min_log2, best.sl,
                    best.order, std::min(per_round, 62 - int(best.order.size())));
       if (sa_half > 0) {
         int lim = std::max(cap, current().max_w);
         Annealer an{C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.search_dtype,
                     opt.chalf_min_log2, lim};
-        an.run(std::max(1L, sa_half / 16), opt.seed + 7 * rounds, 0.03, 0.002);
+        an.run(std::max(1L, sa_half / 16), rseed + 7 * rounds, 0.03, 0.002);
         evaluate_sets(C, leaf_idx, best.tree, best.e);
       }
     }
@@ -660,11 +683,12 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
     bool changed = true;
     while (changed) {
       changed = false;
-      Score cur = current();
+      Score cur = score(C, best.tree, best.e, best.sl, int(best.order.size()), rank_cf, opt.search_dtype,
+                        opt.chalf_min_log2);
       for (size_t i = 0; i < best.order.size(); ++i) {
         Bits s2 = best.sl;
         s2.reset(best.order[i]);
-        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) - 1, cf, opt.search_dtype,
+        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) - 1, rank_cf, opt.search_dtype,
                          opt.chalf_min_log2);
         if (sc.max_w <= cap && sc.total < cur.total) {
           best.sl = s2;
@@ -686,7 +710,7 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
       cand.each([&](int x) {
         Bits s2 = best.sl;
         s2.set(x);
-        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) + 1, cf, opt.search_dtype,
+        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) + 1, rank_cf, opt.search_dtype,
                          opt.chalf_min_log2);
         if (sc.total < bv) { bv = sc.total; bx = x; }
       });
@@ -698,6 +722,23 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
   Score fin = score(C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.search_dtype,
                     opt.chalf_min_log2);
   if (fin.max_w > cap) return "no tree fits the memory cap with the slices allowed";
+  return std::string();
+  }();
+  if (!err.empty()) {
+    if (first_err.empty()) first_err = err;
+    continue;
+  }
+  // rank the complete candidate (tree and slicing) by the ranking cost
+  Score rk = score(C, cand.tree, cand.e, cand.sl, int(cand.order.size()), rank_cf, opt.search_dtype,
+                   opt.chalf_min_log2);
+  if (rk.total < best_rank) {
+    best_rank = rk.total;
+    best = std::move(cand);
+  }
+  }
+  if (!std::isfinite(best_rank)) return first_err.empty() ? "no tree found" : first_err;
+  Score fin = score(C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.search_dtype,
+                    opt.chalf_min_log2);
 
   hp.tree = best.tree;
   hp.node_idx = best.e.idx;

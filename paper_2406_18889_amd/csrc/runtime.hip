@@ -434,6 +434,7 @@ void lf_plan_opts_default(lf_plan_opts* o) {
   o->slices_per_graph = 8;
   o->search_dtype = -1;
   o->autotune = 1;
+  o->restarts = 1;
 }
 
 const char* lf_last_error(void) { return g_err.c_str(); }
@@ -489,6 +490,8 @@ lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits
     po.dtype = o.dtype;
     po.search_dtype = o.search_dtype < 0 ? o.dtype : o.search_dtype;
     po.chalf_min_log2 = o.chalf_min_log2;
+    if (o.restarts < 1 || o.restarts > 64) return fail(LF_INVALID_ARGUMENT, "restarts must be in [1, 64]");
+    po.restarts = o.restarts;
     if (o.n_forced > 0) {
       if (!o.sliced_wires) return fail(LF_INVALID_ARGUMENT, "sliced_wires is NULL");
       for (int t = 0; t < o.n_forced; ++t) {
