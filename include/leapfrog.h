@@ -99,9 +99,9 @@ typedef struct lf_plan_opts {
   int32_t restarts;              /* >= 1: the `restarts` best candidate trees are each
                                     annealed and sliced to the cap; the ranking cost
                                     (cost_model: the learned model, else FLOP + memory)
-                                    of the whole sliced network picks one.  The ranking
-                                    cost also chooses the wires to slice; tree moves
-                                    (annealing) always run on FLOP + memory */
+                                    of the whole sliced network picks one.  The search
+                                    itself (trees, annealing, sliced wires) always runs
+                                    on FLOP + memory */
 } lf_plan_opts;
 
 typedef struct lf_plan_info {

@@ -193,14 +193,17 @@ template <> struct RowLoad<float> {
   }
 };
 
-template <typename TA, typename TB, typename TO, int K>
+template <typename TA, typename TB, typename TO, int K, int RPT>
 __global__ void __launch_bounds__(256) gett_narrow(GettArgs a) {
   __shared__ float2 sB[256];
   __shared__ int64_t cnT[256];
   const int64_t M = int64_t(1) << a.nm;
   const int N = 1 << a.nn;
-  const int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;  // rows of one z per block
-  const int64_t z = (int64_t(blockIdx.x) * blockDim.x) >> a.nm;
+  // a block takes 256 RPT consecutive rows of one z; thread t takes rows
+  // t, t + 256, ..., so that each of its RPT row loads is coalesced across
+  // the block and all of them are in flight together
+  const int64_t r0 = int64_t(blockIdx.x) * (256 * RPT);
+  const int64_t z = r0 >> a.nm;
   const int64_t bz = a.offB ? a.offB[z] : z * N * K;
   const TB* B = static_cast<const TB*>(a.B);
   for (int i = threadIdx.x; i < N * K; i += blockDim.x) {
@@ -209,48 +212,69 @@ __global__ void __launch_bounds__(256) gett_narrow(GettArgs a) {
     sB[i] = make_float2(br, bi);
   }
   for (int i = threadIdx.x; i < N; i += blockDim.x) cnT[i] = scatter_bits(i, a.cn, a.nn);
+  const int64_t abase = a.offA ? a.offA[z] : z * M * K;
+  float ar[RPT][K], ai[RPT][K];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int64_t m = (r0 + threadIdx.x + 256 * j) & (M - 1);
+    RowLoad<TA>::template load<K>(static_cast<const TA*>(a.A) + 2 * (abase + m * K), ar[j], ai[j]);
+  }
   __syncthreads();
-  const int64_t m = r & (M - 1);
-  const int64_t arow = (a.offA ? a.offA[z] : z * M * K) + m * K;
-  float ar[K], ai[K];
-  RowLoad<TA>::template load<K>(static_cast<const TA*>(a.A) + 2 * arow, ar, ai);
-  const int64_t cbase = scatter_bits(z, a.cz, a.nz) + scatter_bits(m, a.cm, a.nm);
+  const int64_t czv = scatter_bits(z, a.cz, a.nz);
   TO* C = static_cast<TO*>(a.C);
   float lmax = 0.0f;
   unsigned lsat = 0;
-  for (int n = 0; n < N; ++n) {
-    float cr = 0.f, ci = 0.f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const float2 b = sB[n * K + k];
-      cr += ar[k] * b.x - ai[k] * b.y;
-      ci += ar[k] * b.y + ai[k] * b.x;
+  for (int j = 0; j < RPT; ++j) {
+    const int64_t m = (r0 + threadIdx.x + 256 * j) & (M - 1);
+    const int64_t cbase = czv + scatter_bits(m, a.cm, a.nm);
+    for (int n = 0; n < N; ++n) {
+      float cr = 0.f, ci = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float2 bv = sB[n * K + k];
+        cr += ar[j][k] * bv.x - ai[j][k] * bv.y;
+        ci += ar[j][k] * bv.y + ai[j][k] * bv.x;
+      }
+      cr *= a.scale;
+      ci *= a.scale;
+      lmax = fmaxf(lmax, fmaxf(fabsf(cr), fabsf(ci)));
+      if (!a.amax_only) lsat += CIO<TO>::store(C, cbase + cnT[n], cr, ci);
     }
-    cr *= a.scale;
-    ci *= a.scale;
-    lmax = fmaxf(lmax, fmaxf(fabsf(cr), fabsf(ci)));
-    if (!a.amax_only) lsat += CIO<TO>::store(C, cbase + cnT[n], cr, ci);
   }
   block_amax_sat(lmax, lsat, a.amax, a.sat);
 }
 
-template <typename TA, typename TB, typename TO>
-static hipError_t launch_narrow(const GettArgs& a, hipStream_t s) {
+template <typename TA, typename TB, typename TO, int K>
+static hipError_t launch_narrow_k(const GettArgs& a, hipStream_t s) {
+  // rows per thread: enough bytes in flight per thread for short rows
+  constexpr int RPT = K <= 2 ? 8 : (K <= 4 ? 4 : (K <= 8 ? 2 : 1));
   const int64_t rows = (int64_t(1) << a.nz) << a.nm;
-  const int64_t blocks = rows / 256;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const dim3 g = dim3(unsigned(blocks)), b = dim3(256);
-  switch (a.nk) {
-    case 0: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 1>), g, b, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 2>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 4>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 8>), g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 16>), g, b, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 32>), g, b, 0, s, a); break;
-    case 6: hipLaunchKernelGGL((gett_narrow<TA, TB, TO, 64>), g, b, 0, s, a); break;
-    default: return hipErrorInvalidValue;
+  const dim3 b = dim3(256);
+  if ((int64_t(1) << a.nm) >= 256 * RPT) {
+    const int64_t blocks = rows / (256 * RPT);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gett_narrow<TA, TB, TO, K, RPT>), dim3(unsigned(blocks)), b, 0, s, a);
+  } else {
+    const int64_t blocks = rows / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gett_narrow<TA, TB, TO, K, 1>), dim3(unsigned(blocks)), b, 0, s, a);
   }
   return hipGetLastError();
+}
+
+template <typename TA, typename TB, typename TO>
+static hipError_t launch_narrow(const GettArgs& a, hipStream_t s) {
+  switch (a.nk) {
+    case 0: return launch_narrow_k<TA, TB, TO, 1>(a, s);
+    case 1: return launch_narrow_k<TA, TB, TO, 2>(a, s);
+    case 2: return launch_narrow_k<TA, TB, TO, 4>(a, s);
+    case 3: return launch_narrow_k<TA, TB, TO, 8>(a, s);
+    case 4: return launch_narrow_k<TA, TB, TO, 16>(a, s);
+    case 5: return launch_narrow_k<TA, TB, TO, 32>(a, s);
+    case 6: return launch_narrow_k<TA, TB, TO, 64>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // --------------------------------------------------------------- MFMA
@@ -509,8 +533,18 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
   constexpr int BG_BK = BK, BG_LDK = BigK<BK>::LDK, CPR = BigK<BK>::CPR;
   constexpr int NA = BM * CPR / 256, NB = BN * CPR / 256;   // 16 B chunks per thread
   constexpr int NBUF = ST >= 2 ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) _Float16 sA[NBUF][BM * BG_LDK];
-  __shared__ __attribute__((aligned(16))) _Float16 sB[NBUF][BN * BG_LDK];
+  // one LDS block: the operand tiles during the K loop, then (whole
+  // complex-half tiles) the result tile, staged for an ordered write-out
+  constexpr bool STAGE = FULL && std::is_same<TO, _Float16>::value;
+  constexpr int SROW = BN + 1;   // staged row (words): odd, so lanes of consecutive m hit distinct banks
+  constexpr int MAIN_BYTES = NBUF * (BM + BN) * BG_LDK * 2;
+  constexpr int STAGE_BYTES = STAGE ? BM * SROW * 4 : 0;
+  constexpr int SMEM = MAIN_BYTES > STAGE_BYTES ? MAIN_BYTES : STAGE_BYTES;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+  typedef _Float16 TileA[BM * BG_LDK];
+  typedef _Float16 TileB[BN * BG_LDK];
+  TileA* sA = reinterpret_cast<TileA*>(smem);
+  TileB* sB = reinterpret_cast<TileB*>(smem + NBUF * BM * BG_LDK * 2);
   __shared__ int64_t cmT[BM];
   __shared__ int64_t cnT[BN];
 
@@ -645,6 +679,78 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
   TO* C = static_cast<TO*>(a.C);
   float lmax = 0.0f;
   unsigned lsat = 0;
+  if constexpr (STAGE) {
+    // Whole complex-half tile: results go to LDS as (re, im) half pairs, then
+    // leave in the order of the output's strides.  The tile's element index
+    // e has one bit per tile bit of m (8) and of n (log2 BN), sorted by the
+    // output stride of that bit; consecutive threads take consecutive e, so
+    // the smallest strides run across lanes and the stores coalesce however
+    // the consumer laid the result out.
+    constexpr int LM = 8, LN = BN == 128 ? 7 : (BN == 64 ? 6 : 5), LT = LM + LN;
+    constexpr int PER = (BM * BN) / 256;   // elements per thread
+    uint32_t* stage = reinterpret_cast<uint32_t*>(smem);
+    __shared__ int64_t hiAddr[PER];
+    __shared__ int hiIdx[PER];
+    __syncthreads();   // every wave is done with the operand tiles
+#pragma unroll
+    for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+      for (int bm = 0; bm < WM; ++bm) {
+        const int ml = wm * 32 * WM + bm * 32 + (lane & 31);
+#pragma unroll
+        for (int v = 0; v < 16; v += 2) {
+          const int nl = (wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1;
+          float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
+          lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+          // saturation counts only values that are stored (not the
+          // calibration pass, which runs unscaled)
+          if (!(fabsf(re) <= HALF_MAX)) { lsat += a.amax_only ? 0 : 1; re = (re != re) ? 0.0f : copysignf(HALF_MAX, re); }
+          if (!(fabsf(im) <= HALF_MAX)) { lsat += a.amax_only ? 0 : 1; im = (im != im) ? 0.0f : copysignf(HALF_MAX, im); }
+          f16x2 h;
+          h[0] = (_Float16)re;
+          h[1] = (_Float16)im;
+          uint32_t wv;
+          __builtin_memcpy(&wv, &h, 4);
+          stage[ml * SROW + nl] = wv;
+        }
+      }
+    // sort the tile bits by output stride (every thread, same result)
+    int64_t st[LT];
+    int bit[LT];   // tile bit: 0..LM-1 are m bits, LM.. are n bits
+#pragma unroll
+    for (int i = 0; i < LT; ++i) {
+      bit[i] = i;
+      st[i] = i < LM ? a.cm[i] : a.cn[i - LM];
+    }
+    for (int i = 1; i < LT; ++i)
+      for (int j = i; j > 0 && st[j] < st[j - 1]; --j) {
+        const int64_t ts = st[j]; st[j] = st[j - 1]; st[j - 1] = ts;
+        const int tb = bit[j]; bit[j] = bit[j - 1]; bit[j - 1] = tb;
+      }
+    // element e = tid + 256 j: its low 8 bits come from tid, the rest from j
+    auto split = [&](int e, int lo, int hi, int64_t& addr, int& idx) {
+      addr = 0;
+      int ml = 0, nl = 0;
+      for (int i = lo; i < hi; ++i)
+        if ((e >> (i - lo)) & 1) {
+          addr += st[i];
+          if (bit[i] < LM) ml |= 1 << bit[i];
+          else nl |= 1 << (bit[i] - LM);
+        }
+      idx = ml * SROW + nl;
+    };
+    int64_t loAddr;
+    int loIdx;
+    split(tid, 0, 8, loAddr, loIdx);
+    if (tid < PER) split(tid, 8, LT, hiAddr[tid], hiIdx[tid]);
+    __syncthreads();
+    if (!a.amax_only) {
+      const int64_t base = czv + cmT[0] + cnT[0] + loAddr;
+      uint32_t* Cw = reinterpret_cast<uint32_t*>(C);
+#pragma unroll 8
+      for (int j = 0; j < PER; ++j) Cw[base + hiAddr[j]] = stage[loIdx + hiIdx[j]];
+    }
+  } else {
 #pragma unroll
   for (int bn = 0; bn < WN; ++bn)
 #pragma unroll
@@ -662,6 +768,7 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
         if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
       }
     }
+  }
   block_amax_sat(lmax, lsat, a.amax, a.sat);
 }
 

@@ -556,11 +556,11 @@ const CostFn& default_cost() {
 std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& hp,
                          const CostFn* rank_cost) {
   hp = HostPlan();
-  // the tree search (candidate ranking, annealing) runs on the FLOP +
-  // memory cost; `rank_cost` (the learned model, when given) ranks complete
-  // alternatives: which wire to slice next (each choice scored over the
-  // whole sliced network), which slices to drop, and which of the refined
-  // candidates to keep
+  // the search (candidate trees, annealing, slicing) runs on the FLOP +
+  // memory cost; `rank_cost` (the learned model, when given) picks which of
+  // the refined candidates, each a tree with its slicing, is kept.  Used
+  // inside annealing or for the choice of sliced wires, the learned cost
+  // steered the search to plans with more slices and a longer total time.
   const CostFn& cf = default_cost();
   const CostFn& rank_cf = rank_cost ? *rank_cost : default_cost();
   Ctx C(net);
@@ -669,7 +669,7 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
     for (Score sc = current(); sc.max_w > cap; sc = current(), ++rounds) {
       if (int(best.order.size()) >= 62) return "no tree fits the memory cap within 62 sliced wires";
       int target = std::max(cap, sc.max_w - per_round);
-      greedy_slice(C, best.tree, best.e, target, rank_cf, opt.search_dtype, opt.chalf_min_log2, best.sl,
+      greedy_slice(C, best.tree, best.e, target, cf, opt.search_dtype, opt.chalf_min_log2, best.sl,
                    best.order, std::min(per_round, 62 - int(best.order.size())));
       if (sa_half > 0) {
         int lim = std::max(cap, current().max_w);
@@ -683,12 +683,11 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
     bool changed = true;
     while (changed) {
       changed = false;
-      Score cur = score(C, best.tree, best.e, best.sl, int(best.order.size()), rank_cf, opt.search_dtype,
-                        opt.chalf_min_log2);
+      Score cur = current();
       for (size_t i = 0; i < best.order.size(); ++i) {
         Bits s2 = best.sl;
         s2.reset(best.order[i]);
-        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) - 1, rank_cf, opt.search_dtype,
+        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) - 1, cf, opt.search_dtype,
                          opt.chalf_min_log2);
         if (sc.max_w <= cap && sc.total < cur.total) {
           best.sl = s2;
@@ -710,7 +709,7 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
       cand.each([&](int x) {
         Bits s2 = best.sl;
         s2.set(x);
-        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) + 1, rank_cf, opt.search_dtype,
+        Score sc = score(C, best.tree, best.e, s2, int(best.order.size()) + 1, cf, opt.search_dtype,
                          opt.chalf_min_log2);
         if (sc.total < bv) { bv = sc.total; bx = x; }
       });

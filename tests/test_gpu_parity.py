@@ -87,6 +87,8 @@ SHAPES = [
     (0, 9, 6, 9), (1, 4, 4, 1), (0, 5, 4, 4), (0, 12, 8, 4), (0, 8, 6, 1), (2, 7, 5, 0),
     (0, 9, 7, 2), (1, 9, 3, 3), (0, 8, 0, 6), (2, 8, 4, 0), (0, 13, 2, 2), (0, 10, 4, 4),
     (1, 8, 8, 0), (1, 10, 9, 3), (0, 9, 8, 3), (2, 7, 4, 5), (0, 6, 3, 6),
+    # whole tiles of the large kernels (bounds-free loop, ordered write-out)
+    (1, 9, 8, 5), (0, 10, 7, 6), (2, 8, 7, 7),
 ]
 
 
