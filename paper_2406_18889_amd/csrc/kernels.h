@@ -44,7 +44,7 @@ struct GettArgs {
 // and M >= 256; K_MFMA_WIDE: 256 x 128 complex tile, complex-half only;
 // K_MFMA_DB: the 256 x 128 tile with double-buffered LDS, complex-half
 // only; K_MFMA_DEEP: the 256 x 128 tile with 64-deep K steps (one LDS
-// buffer).  All large tiles walk the tiles in an XCD-aware order.
+// buffer).
 // K_SKINNY: MFMA on 32-row groups of A against a B' of at most 32 rows held
 // in registers (N <= 16, 4 <= K <= 64), complex-half A, B either type.
 enum KernelId : int {
