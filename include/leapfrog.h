@@ -274,7 +274,8 @@ lf_status lf_plan_kernel_times(lf_plan* plan, double* total_ms, int64_t* launche
  * tile (complex-half), 5 the 256 x 128 tile with double-buffered LDS
  * (complex-half), 6 the 256 x 128 tile with 64-deep K steps (complex-half),
  * 7 MFMA on 32-row groups against a B of 2^nn <= 16 rows held in registers
- * (complex-half A, 2 <= nk <= 6), -1 the default choice; a kernel that does
+ * (complex-half A, 2 <= nk <= 6), 8 and 9 kernels 2 and 5 with tiles dealt
+ * to the XCDs in contiguous groups, -1 the default choice; a kernel that does
  * not apply to the
  * shape or dtype falls back to 0.  Device pointers owned by the caller; A and
  * B 16-byte aligned.  Limits: nz <= 20, nm, nn <= 40.  Errors:

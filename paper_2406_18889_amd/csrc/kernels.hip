@@ -473,9 +473,11 @@ __global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
 // the MFMA work that covers the HBM latency of the next step's loads, which
 // the register budget beside a 4 x 4 wave tile allows only once.
 //
-// Tiles are numbered n fastest, then m, then z: consecutive blocks share an
-// A panel.  (A renumbering that gave each XCD a contiguous range of tiles in
-// groups of 8 m-tiles measured 5% slower on the fat steps.)
+// Tile order (a.tile_order): 0 numbers tiles n fastest, then m, then z;
+// 1 gives each XCD a contiguous range of tiles in groups of 8 m-tiles.
+// With order 0 every XCD touches every A panel (HBM reads of A up to 8x);
+// order 1 reads A once and B once per group, but measured 5% slower on fat,
+// compute-bound steps, so the autotuner picks per step shape.
 //
 // FULL (chosen at launch: M, N multiples of the block tile and K of the K
 // step, so every tile is whole) drops the bounds tests from the loads: a
@@ -513,12 +515,25 @@ template <int WM, int WN> struct BigTile {
   static constexpr int BN = 32 * WN;   // complex n per block
 };
 
-__device__ __forceinline__ void big_tile_of(int64_t bid, int64_t mt, int64_t nt, int64_t& z, int64_t& tm,
-                                            int64_t& tn) {
-  tn = bid % nt;
-  bid /= nt;
-  tm = bid % mt;
-  z = bid / mt;
+__device__ __forceinline__ void big_tile_of(int64_t bid, int64_t nblk, int order, int64_t mt, int64_t nt,
+                                            int64_t& z, int64_t& tm, int64_t& tn) {
+  if (order == 0) {
+    tn = bid % nt;
+    bid /= nt;
+    tm = bid % mt;
+    z = bid / mt;
+    return;
+  }
+  // blocks are dealt to the 8 XCDs round-robin: give each XCD a contiguous
+  // range of tiles, walked in groups of 8 m-tiles that sweep n together
+  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  const int64_t per_z = mt * nt;
+  z = bid / per_z;
+  const int64_t r = bid - z * per_z;
+  const int64_t per_group = 8 * nt, g = r / per_group, rg = r - g * per_group;
+  const int64_t first = g * 8, gsz = mt - first < 8 ? mt - first : 8;
+  tm = first + rg % gsz;
+  tn = rg / gsz;
 }
 
 template <typename TO, int WM, int WN, int MINB, int ST, int BK, bool FULL>
@@ -546,7 +561,7 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
   const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN;
   int64_t z, tm, tn;
-  big_tile_of(blockIdx.x, mt, nt, z, tm, tn);
+  big_tile_of(blockIdx.x, gridDim.x, a.tile_order, mt, nt, z, tm, tn);
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -900,7 +915,8 @@ bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
   (void)nk;
   if (kernel == K_THIN) return true;
   if (kernel == K_MFMA) return nm >= 5 && nn >= 4;
-  if (kernel == K_MFMA_BIG) return in_dt == 1 && nm >= 7 && nn >= 5;
+  if (kernel == K_MFMA_BIG || kernel == K_MFMA_BIG_X) return in_dt == 1 && nm >= 7 && nn >= 5;
+  if (kernel == K_MFMA_DB_X) return in_dt == 1 && nm >= 7 && nn >= 6;
   if (kernel == K_MFMA_WIDE) return in_dt == 1 && nm >= 7 && nn >= 6;
   if (kernel == K_MFMA_DB || kernel == K_MFMA_DEEP) return in_dt == 1 && nm >= 7 && nn >= 6;
   if (kernel == K_NARROW) return nm >= 8 && nk <= 6 && nn <= 8 && nn + nk <= 8;
@@ -945,6 +961,11 @@ static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((gett_mfma<TI, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
   } else {
     if constexpr (std::is_same<TI, _Float16>::value) {
+      if (kernel == K_MFMA_BIG_X || kernel == K_MFMA_DB_X) {
+        GettArgs b = a;
+        b.tile_order = 1;
+        return kernel == K_MFMA_BIG_X ? launch_big<TO, 4, 2, 2, 1, 32>(b, s) : launch_big<TO, 4, 4, 1, 2, 32>(b, s);
+      }
       if (kernel == K_MFMA_BIG) return launch_big<TO, 4, 2, 2, 1, 32>(a, s);
       if (kernel == K_MFMA_WIDE) return launch_big<TO, 4, 4, 1, 1, 32>(a, s);
       if (kernel == K_MFMA_DB) return launch_big<TO, 4, 4, 1, 2, 32>(a, s);
