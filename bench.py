@@ -22,11 +22,12 @@ if ROOT not in sys.path:
 
 MI355X = {"hbm_gbs": 8000.0, "fp16_tflops": 2500.0, "fp32_tflops": 157.3}
 # kernel ids of the contraction steps; the large tiles are instances of
-# gett_mfma_big<TO, WM, WN, MINB, ST, BK, FULL>, named here by WM,WN,MINB,ST,BK
-KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big<4,2,2,1,32>", 3: "gett_narrow",
-                4: "gett_mfma_big<4,4,1,1,32>", 5: "gett_mfma_big<4,4,1,2,32>",
-                6: "gett_mfma_big<4,4,1,1,64>", 7: "gett_skinny",
-                8: "gett_mfma_big<4,2,2,1,32> xcd-order", 9: "gett_mfma_big<4,4,1,2,32> xcd-order"}
+# gett_mfma_big<TO, WM, WN, MINB, ST, BK, FULL, ORDER>, named here by
+# WM,WN,MINB,ST,BK,ORDER (a profiler lists FULL true and false separately)
+KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big<4,2,2,1,32,0>", 3: "gett_narrow",
+                4: "gett_mfma_big<4,4,1,1,32,0>", 5: "gett_mfma_big<4,4,1,2,32,0>",
+                6: "gett_mfma_big<4,4,1,1,64,0>", 7: "gett_skinny",
+                8: "gett_mfma_big<4,2,2,1,32,1>", 9: "gett_mfma_big<4,4,1,2,32,1>"}
 # planner settings per workload (search effort, not inputs)
 PLAN_OPTS = {"rqc53": {"sa_iters": 4_000_000}}
 
@@ -51,8 +52,7 @@ def traffic_for(workload, dtype, kernel):
         return None
     if d.get("source_hash") != source_hash():
         return None
-    # the counters see a kernel instance, whatever tile order it ran with
-    return d.get("bytes_per_launch", {}).get(kernel.replace(" xcd-order", ""))
+    return d.get("bytes_per_launch", {}).get(kernel)
 
 
 def parse():

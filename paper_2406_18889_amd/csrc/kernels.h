@@ -31,7 +31,6 @@ struct GettArgs {
   int nz, nm, nn, nk;
   float scale;
   int amax_only;      // 1: record the largest |re|,|im| only, store nothing
-  int tile_order;     // large MFMA tiles: 0 n fastest, 1 per-XCD ranges in groups of 8 m-tiles
   float* amax;        // nullable: running max of |re|,|im| of stored values (as bits)
   unsigned* sat;      // nullable: count of values clamped to the half range
   int64_t cz[MAXZ];

@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
 // the MFMA work that covers the HBM latency of the next step's loads, which
 // the register budget beside a 4 x 4 wave tile allows only once.
 //
-// Tile order (a.tile_order): 0 numbers tiles n fastest, then m, then z;
+// Tile order (ORDER): 0 numbers tiles n fastest, then m, then z;
 // 1 gives each XCD a contiguous range of tiles in groups of 8 m-tiles.
 // With order 0 every XCD touches every A panel (HBM reads of A up to 8x);
 // order 1 reads A once and B once per group, but measured 5% slower on fat,
@@ -536,7 +536,7 @@ __device__ __forceinline__ void big_tile_of(int64_t bid, int64_t nblk, int order
   tn = rg / gsz;
 }
 
-template <typename TO, int WM, int WN, int MINB, int ST, int BK, bool FULL>
+template <typename TO, int WM, int WN, int MINB, int ST, int BK, bool FULL, int ORDER>
 __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
   constexpr int BM = BigTile<WM, WN>::BM, BN = BigTile<WM, WN>::BN;
   constexpr int BG_BK = BK, BG_LDK = BigK<BK>::LDK, CPR = BigK<BK>::CPR;
@@ -561,7 +561,7 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
   const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN;
   int64_t z, tm, tn;
-  big_tile_of(blockIdx.x, gridDim.x, a.tile_order, mt, nt, z, tm, tn);
+  big_tile_of(blockIdx.x, gridDim.x, ORDER, mt, nt, z, tm, tn);
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -933,7 +933,7 @@ static hipError_t launch_thin(const GettArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename TO, int WM, int WN, int MINB, int ST, int BK>
+template <typename TO, int WM, int WN, int MINB, int ST, int BK, int ORDER = 0>
 static hipError_t launch_big(const GettArgs& a, hipStream_t s) {
   using T = BigTile<WM, WN>;
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
@@ -941,9 +941,11 @@ static hipError_t launch_big(const GettArgs& a, hipStream_t s) {
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const bool full = M % T::BM == 0 && N % T::BN == 0 && K % BK == 0;
   if (full)
-    hipLaunchKernelGGL((gett_mfma_big<TO, WM, WN, MINB, ST, BK, true>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gett_mfma_big<TO, WM, WN, MINB, ST, BK, true, ORDER>), dim3(unsigned(blocks)), dim3(256), 0, s,
+                       a);
   else
-    hipLaunchKernelGGL((gett_mfma_big<TO, WM, WN, MINB, ST, BK, false>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gett_mfma_big<TO, WM, WN, MINB, ST, BK, false, ORDER>), dim3(unsigned(blocks)), dim3(256), 0,
+                       s, a);
   return hipGetLastError();
 }
 
@@ -961,11 +963,8 @@ static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((gett_mfma<TI, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
   } else {
     if constexpr (std::is_same<TI, _Float16>::value) {
-      if (kernel == K_MFMA_BIG_X || kernel == K_MFMA_DB_X) {
-        GettArgs b = a;
-        b.tile_order = 1;
-        return kernel == K_MFMA_BIG_X ? launch_big<TO, 4, 2, 2, 1, 32>(b, s) : launch_big<TO, 4, 4, 1, 2, 32>(b, s);
-      }
+      if (kernel == K_MFMA_BIG_X) return launch_big<TO, 4, 2, 2, 1, 32, 1>(a, s);
+      if (kernel == K_MFMA_DB_X) return launch_big<TO, 4, 4, 1, 2, 32, 1>(a, s);
       if (kernel == K_MFMA_BIG) return launch_big<TO, 4, 2, 2, 1, 32>(a, s);
       if (kernel == K_MFMA_WIDE) return launch_big<TO, 4, 4, 1, 1, 32>(a, s);
       if (kernel == K_MFMA_DB) return launch_big<TO, 4, 4, 1, 2, 32>(a, s);
