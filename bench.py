@@ -27,7 +27,8 @@ MI355X = {"hbm_gbs": 8000.0, "fp16_tflops": 2500.0, "fp32_tflops": 157.3}
 KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big<4,2,2,1,32,0>", 3: "gett_narrow",
                 4: "gett_mfma_big<4,4,1,1,32,0>", 5: "gett_mfma_big<4,4,1,2,32,0>",
                 6: "gett_mfma_big<4,4,1,1,64,0>", 7: "gett_skinny",
-                8: "gett_mfma_big<4,2,2,1,32,1>", 9: "gett_mfma_big<4,4,1,2,32,1>"}
+                8: "gett_mfma_big<4,2,2,1,32,1>", 9: "gett_mfma_big<4,4,1,2,32,1>",
+                10: "gett_mfma_big<4,4,1,1,32,1>"}
 # planner settings per workload (search effort, not inputs)
 PLAN_OPTS = {"rqc53": {"sa_iters": 4_000_000}}
 

@@ -274,8 +274,8 @@ lf_status lf_plan_kernel_times(lf_plan* plan, double* total_ms, int64_t* launche
  * tile (complex-half), 5 the 256 x 128 tile with double-buffered LDS
  * (complex-half), 6 the 256 x 128 tile with 64-deep K steps (complex-half),
  * 7 MFMA on 32-row groups against a B of 2^nn <= 16 rows held in registers
- * (complex-half A, 2 <= nk <= 6), 8 and 9 kernels 2 and 5 with tiles dealt
- * to the XCDs in contiguous groups, -1 the default choice; a kernel that does
+ * (complex-half A, 2 <= nk <= 6), 8, 9 and 10 kernels 2, 5 and 4 with tiles
+ * dealt to the XCDs in contiguous groups, -1 the default choice; a kernel that does
  * not apply to the
  * shape or dtype falls back to 0.  Device pointers owned by the caller; A and
  * B 16-byte aligned.  Limits: nz <= 20, nm, nn <= 40.  Errors:
@@ -320,6 +320,25 @@ lf_status lf_mlp_gradients(const float* params, int32_t n_in, int32_t hidden, co
 /* One Adam update (step counts from 1) of params with moments m, v. */
 lf_status lf_mlp_adam_step(float* params, float* m, float* v, const float* grads, int64_t n_params,
                            int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
+
+/*
+ * Trains the network on the GPU with the library's own kernels (the
+ * extension's learned part): X [n][n_in] and T [n] are host arrays of raw
+ * features and targets (log seconds); they are standardised (population
+ * mean and deviation, written to x_mean [n_in], x_std [n_in], y_mean,
+ * y_std, host) and the parameters (device, [lf_mlp_sizes n_params],
+ * initialised by the caller) are fitted by mean squared error with Adam
+ * (beta 0.9, 0.999, eps 1e-8), `epochs` passes over a seeded shuffle in
+ * batches of `batch` rows (a last partial batch is dropped), learning rate
+ * lr * (1 + cos(pi epoch / epochs)) / 2.  curve (host [epochs], nullable)
+ * receives the mean batch loss per epoch.  Device temporaries are allocated
+ * and freed inside; synchronous on stream.  Errors: LF_INVALID_ARGUMENT,
+ * LF_HIP_ERROR.
+ */
+lf_status lf_costmodel_train(const float* X, const float* T, int64_t n, int32_t n_in, int32_t hidden,
+                             int32_t epochs, int32_t batch, float lr, uint64_t seed, float* params,
+                             float* x_mean, float* x_std, float* y_mean, float* y_std, float* curve,
+                             void* stream);
 
 /* Loads a trained network (host copy of params, n_in == LF_N_FEATURES) with
  * its feature standardisation (x - x_mean[i]) / x_std[i] and target

@@ -113,6 +113,9 @@ SIGNATURES = {
                                           _P, _P, ctypes.c_uint64, _P]),
     "lf_mlp_adam_step": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
                                           ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
+    "lf_costmodel_train": (ctypes.c_int32, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
+                                            _P, _P, _P, _P, _P, _P, _P]),
     "lf_costmodel_load": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_float), ctypes.c_int32, ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                            ctypes.c_float, ctypes.c_float]),

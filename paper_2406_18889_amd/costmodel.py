@@ -116,41 +116,35 @@ class CostNet:
               "lf_mlp_adam_step")
 
 
-def standardize(X: np.ndarray, t: np.ndarray):
-    xm = X.mean(0).astype(np.float32)
-    xs = X.std(0).astype(np.float32)
-    xs[xs <= 0] = 1.0
-    ym, ys = float(t.mean()), float(t.std() or 1.0)
-    return xm, xs, ym, ys
-
-
 def train(X: np.ndarray, t: np.ndarray, epochs: int = 60, batch: int = 512, lr: float = 2e-3,
           seed: int = 0, log=None):
-    """Fits the network on (features, log seconds); returns a model dict and
-    the per-epoch training loss (standardised units)."""
+    """Fits the network on (features, log seconds) with lf_costmodel_train
+    (standardisation, shuffling, batches, gradients and Adam all in the
+    library); returns a model dict and the per-epoch training loss
+    (standardised units)."""
     import torch
-    xm, xs, ym, ys = standardize(X, t)
-    Xn = torch.from_numpy(((X - xm) / xs).astype(np.float32)).cuda()
-    tn = torch.from_numpy(((t - ym) / ys).astype(np.float32)).cuda()
-    net = CostNet(init_params(seed=seed), max_batch=max(batch, 4096))
-    rng = np.random.Generator(np.random.PCG64(seed + 1))
-    curve = []
-    n = X.shape[0]
-    for ep in range(epochs):
-        perm = torch.from_numpy(rng.permutation(n)).cuda()
-        tot, cnt = 0.0, 0
-        step_lr = lr * 0.5 * (1 + math.cos(math.pi * ep / epochs))
-        for s in range(0, n - batch + 1, batch):
-            idx = perm[s:s + batch]
-            _, loss = net.gradients(Xn[idx], tn[idx])
-            net.adam(lr=step_lr)
-            tot += float(loss.item())
-            cnt += 1
-        curve.append(tot / max(1, cnt))
-        if log:
-            log(f"epoch {ep} loss {curve[-1]:.4f}")
-    model = {"params": net.p.cpu().numpy(), "x_mean": xm, "x_std": xs, "y_mean": ym, "y_std": ys}
-    return model, curve
+    X = np.ascontiguousarray(X, np.float32)
+    t = np.ascontiguousarray(t, np.float32)
+    n, n_in = X.shape
+    p = torch.from_numpy(init_params(n_in, HIDDEN, seed=seed)).cuda()
+    xm = np.zeros(n_in, np.float32)
+    xs = np.zeros(n_in, np.float32)
+    ym = ctypes.c_float()
+    ys = ctypes.c_float()
+    curve = np.zeros(epochs, np.float32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    check(_lib.load().lf_costmodel_train(X.ctypes.data_as(fp), t.ctypes.data_as(fp), n, n_in, HIDDEN,
+                                         epochs, batch, lr, seed, ctypes.c_void_p(p.data_ptr()),
+                                         xm.ctypes.data_as(fp), xs.ctypes.data_as(fp), ctypes.byref(ym),
+                                         ctypes.byref(ys), curve.ctypes.data_as(fp),
+                                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+          "lf_costmodel_train")
+    if log:
+        for ep, v in enumerate(curve):
+            log(f"epoch {ep} loss {v:.4f}")
+    model = {"params": p.cpu().numpy(), "x_mean": xm, "x_std": xs, "y_mean": float(ym.value),
+             "y_std": float(ys.value)}
+    return model, [float(v) for v in curve]
 
 
 def predict(model, X: np.ndarray) -> np.ndarray:

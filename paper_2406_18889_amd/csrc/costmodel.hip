@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <mutex>
+#include <random>
 #include <unordered_map>
 #include <vector>
 
@@ -137,7 +138,122 @@ namespace {
 thread_local std::string g_cm_err;
 }
 
+namespace {
+
+__global__ void __launch_bounds__(256) gather_rows(const float* X, const float* T, const int* idx, int64_t rows,
+                                                   int n_in, float* Xb, float* Tb) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= rows * n_in) return;
+  const int64_t r = i / n_in, c = i - r * n_in;
+  const int64_t src = idx[r];
+  Xb[i] = X[src * n_in + c];
+  if (c == 0) Tb[r] = T[src];
+}
+
+__global__ void add_into(float* acc, const float* x) {
+  if (threadIdx.x == 0) acc[0] += x[0];
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+}  // namespace
+
 extern "C" {
+
+lf_status lf_costmodel_train(const float* X, const float* T, int64_t n, int32_t n_in, int32_t hidden,
+                             int32_t epochs, int32_t batch, float lr, uint64_t seed, float* params,
+                             float* x_mean, float* x_std, float* y_mean, float* y_std, float* curve,
+                             void* stream) {
+  if (!X || !T || !params || !x_mean || !x_std || !y_mean || !y_std || n_in < 1 || hidden < 1 ||
+      epochs < 1 || batch < 1 || n < batch || n > (int64_t(1) << 30) || !(lr > 0))
+    return LF_INVALID_ARGUMENT;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // standardisation of features and targets (population mean and deviation)
+  std::vector<double> xm(n_in, 0.0), xs(n_in, 0.0);
+  double ym = 0.0, ys = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int c = 0; c < n_in; ++c) xm[c] += X[i * n_in + c];
+    ym += T[i];
+  }
+  for (int c = 0; c < n_in; ++c) xm[c] /= double(n);
+  ym /= double(n);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int c = 0; c < n_in; ++c) {
+      const double d = X[i * n_in + c] - xm[c];
+      xs[c] += d * d;
+    }
+    ys += (T[i] - ym) * (T[i] - ym);
+  }
+  std::vector<float> Xn(size_t(n) * n_in), Tn(n);
+  for (int c = 0; c < n_in; ++c) {
+    xs[c] = std::sqrt(xs[c] / double(n));
+    x_mean[c] = float(xm[c]);
+    x_std[c] = xs[c] > 0 ? float(xs[c]) : 1.0f;
+  }
+  ys = std::sqrt(ys / double(n));
+  *y_mean = float(ym);
+  *y_std = ys > 0 ? float(ys) : 1.0f;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int c = 0; c < n_in; ++c) Xn[i * n_in + c] = (X[i * n_in + c] - x_mean[c]) / x_std[c];
+    Tn[i] = (T[i] - *y_mean) / *y_std;
+  }
+  // device buffers for one training run
+  const int64_t np = lf::mlp_param_count(n_in, hidden);
+  const uint64_t wsb = lf::mlp_workspace_bytes(hidden, batch);
+  DevBuf dX, dT, dIdx, dXb, dTb, dM, dV, dG, dLoss, dWs;
+  if (hipMalloc(&dX.p, sizeof(float) * Xn.size()) || hipMalloc(&dT.p, sizeof(float) * n) ||
+      hipMalloc(&dIdx.p, sizeof(int) * n) || hipMalloc(&dXb.p, sizeof(float) * batch * n_in) ||
+      hipMalloc(&dTb.p, sizeof(float) * batch) || hipMalloc(&dM.p, sizeof(float) * np) ||
+      hipMalloc(&dV.p, sizeof(float) * np) || hipMalloc(&dG.p, sizeof(float) * np) ||
+      hipMalloc(&dLoss.p, sizeof(float) * 2) || hipMalloc(&dWs.p, wsb))
+    return LF_HIP_ERROR;
+  float* fX = static_cast<float*>(dX.p);
+  float* fT = static_cast<float*>(dT.p);
+  int* iIdx = static_cast<int*>(dIdx.p);
+  float* fXb = static_cast<float*>(dXb.p);
+  float* fTb = static_cast<float*>(dTb.p);
+  float* fLoss = static_cast<float*>(dLoss.p);   // [0] batch loss, [1] epoch sum
+  if (hipMemcpyAsync(fX, Xn.data(), sizeof(float) * Xn.size(), hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(fT, Tn.data(), sizeof(float) * n, hipMemcpyHostToDevice, st) ||
+      hipMemsetAsync(dM.p, 0, sizeof(float) * np, st) || hipMemsetAsync(dV.p, 0, sizeof(float) * np, st))
+    return LF_HIP_ERROR;
+  std::mt19937_64 rng(seed);
+  std::vector<int> perm(n);
+  int step = 0;
+  const int64_t nb = n / batch;
+  const int64_t rows = int64_t(batch) * n_in;
+  for (int ep = 0; ep < epochs; ++ep) {
+    for (int64_t i = 0; i < n; ++i) perm[i] = int(i);
+    for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[std::uniform_int_distribution<int64_t>(0, i)(rng)]);
+    // cosine schedule over the epochs
+    const float lr_ep = float(lr * 0.5 * (1.0 + std::cos(M_PI * double(ep) / double(epochs))));
+    if (hipMemcpyAsync(iIdx, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) ||
+        hipMemsetAsync(fLoss + 1, 0, sizeof(float), st))
+      return LF_HIP_ERROR;
+    for (int64_t b = 0; b < nb; ++b) {
+      hipLaunchKernelGGL(gather_rows, dim3(unsigned((rows + 255) / 256)), dim3(256), 0, st, fX, fT,
+                         iIdx + b * batch, int64_t(batch), n_in, fXb, fTb);
+      hipError_t e = lf::mlp_gradients(params, n_in, hidden, fXb, fTb, batch, static_cast<float*>(dG.p), fLoss,
+                                   static_cast<float*>(dWs.p), st);
+      if (e) return LF_HIP_ERROR;
+      hipLaunchKernelGGL(add_into, dim3(1), dim3(64), 0, st, fLoss + 1, fLoss);
+      e = lf::mlp_adam(params, static_cast<float*>(dM.p), static_cast<float*>(dV.p), static_cast<float*>(dG.p), np,
+                   ++step, lr_ep, 0.9f, 0.999f, 1e-8f, st);
+      if (e) return LF_HIP_ERROR;
+    }
+    if (curve) {
+      float sum = 0;
+      if (hipMemcpyAsync(&sum, fLoss + 1, sizeof(float), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st))
+        return LF_HIP_ERROR;
+      curve[ep] = sum / float(nb);
+    }
+  }
+  if (hipStreamSynchronize(st) || hipGetLastError()) return LF_HIP_ERROR;
+  return LF_OK;
+}
 
 lf_status lf_step_features(int32_t nz, int32_t nm, int32_t nn, int32_t nk, int32_t dtype, float* out) {
   if (!out || nz < 0 || nm < 0 || nn < 0 || nk < 0 || (dtype != 0 && dtype != 1)) return LF_INVALID_ARGUMENT;

@@ -916,7 +916,7 @@ bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
   if (kernel == K_THIN) return true;
   if (kernel == K_MFMA) return nm >= 5 && nn >= 4;
   if (kernel == K_MFMA_BIG || kernel == K_MFMA_BIG_X) return in_dt == 1 && nm >= 7 && nn >= 5;
-  if (kernel == K_MFMA_DB_X) return in_dt == 1 && nm >= 7 && nn >= 6;
+  if (kernel == K_MFMA_DB_X || kernel == K_MFMA_WIDE_X) return in_dt == 1 && nm >= 7 && nn >= 6;
   if (kernel == K_MFMA_WIDE) return in_dt == 1 && nm >= 7 && nn >= 6;
   if (kernel == K_MFMA_DB || kernel == K_MFMA_DEEP) return in_dt == 1 && nm >= 7 && nn >= 6;
   if (kernel == K_NARROW) return nm >= 8 && nk <= 6 && nn <= 8 && nn + nk <= 8;
@@ -965,6 +965,7 @@ static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
     if constexpr (std::is_same<TI, _Float16>::value) {
       if (kernel == K_MFMA_BIG_X) return launch_big<TO, 4, 2, 2, 1, 32, 1>(a, s);
       if (kernel == K_MFMA_DB_X) return launch_big<TO, 4, 4, 1, 2, 32, 1>(a, s);
+      if (kernel == K_MFMA_WIDE_X) return launch_big<TO, 4, 4, 1, 1, 32, 1>(a, s);
       if (kernel == K_MFMA_BIG) return launch_big<TO, 4, 2, 2, 1, 32>(a, s);
       if (kernel == K_MFMA_WIDE) return launch_big<TO, 4, 4, 1, 1, 32>(a, s);
       if (kernel == K_MFMA_DB) return launch_big<TO, 4, 4, 1, 2, 32>(a, s);

@@ -100,7 +100,7 @@ def _applicable(kernel, dt, shape):
         return dt == "chalf" and nm >= 7 and nn >= 5
     if kernel == 3:
         return nm >= 8 and nk <= 6 and nn <= 8 and nn + nk <= 8
-    if kernel in (4, 5, 6, 9):
+    if kernel in (4, 5, 6, 9, 10):
         return dt == "chalf" and nm >= 7 and nn >= 6
     if kernel == 7:
         return dt == "chalf" and nn <= 4 and 2 <= nk <= 6 and nm >= (6 if nk == 6 else 7)
@@ -131,7 +131,7 @@ def _to_half_pairs(x, e):
     return torch.from_numpy(v.astype(np.float16)).cuda()
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_pair_chalf(lf, kernel, shape):
     nz, nm, nn, nk = shape
