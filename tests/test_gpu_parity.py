@@ -281,6 +281,30 @@ def test_graph_launch_matches_stream(lf):
     assert torch.equal(a, b2)
 
 
+def test_live_kernel_timing_counts_launches(lf):
+    """lf_plan_time_kernel brackets exactly the launches of the chosen
+    kernel inside ordinary contractions (what bench.py's roofline divides
+    by), and leaves the results unchanged."""
+    _, _, _, _, plan = _small_sliced(lf)
+    ref = plan.contract(0, 16)
+    torch.cuda.synchronize()
+    dims, _, _ = plan.steps()
+    var = dims[:, 4] == 1
+    kernel = int(np.bincount(dims[var, 7]).argmax())
+    per_slice = int((var & (dims[:, 7] == kernel)).sum())
+    plan.time_kernel(kernel, reserve=per_slice * 16)
+    got = plan.contract(0, 16)
+    total_ms, n, per_ms, per_n = plan.kernel_times()
+    plan.time_kernel(-1)
+    assert n == per_slice * 16
+    assert int(per_n.sum()) == n and bool(((per_n > 0) == (var & (dims[:, 7] == kernel))).all())
+    assert total_ms > 0 and abs(float(per_ms.sum()) - total_ms) < 1e-6 * max(1.0, total_ms)
+    assert torch.equal(got, ref)
+    # the counters restart after a read; timing off records nothing
+    plan.contract(0, 4, got)
+    assert plan.kernel_times()[1] == 0
+
+
 def test_complex_half_small(lf):
     c, o, cb, mid, plan = _small_sliced(lf, dtype="chalf", chalf_min=6)
     assert plan.info()["n_half_steps"] > 0
