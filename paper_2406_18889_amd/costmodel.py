@@ -267,11 +267,11 @@ def collect(target_steps: int = 50_000, seed: int = 0, reps: int = 2, log=print,
 
 def compare_rankings(model, n_circuits: int = 6, restarts: int = 4, sa_iters: int = 2_000_000,
                      seed: int = 99, slices: int = 6, log=print):
-    """End-to-end comparison of the two ranking costs, measured runtime as
-    the judge: for seeded 53-qubit, 20-cycle circuits (cap 2^28, 256 closed
+    """End-to-end comparison of the two ranking costs, decided by measured
+    runtime: for seeded 53-qubit, 20-cycle circuits (cap 2^28, 256 closed
     strings, 10 open qubits, complex-half), plans searched with the same
-    seeds and restarts, the wires to slice and the candidate kept chosen by
-    FLOP + memory or by the network; each plan's slices/s is measured and
+    seeds and restarts, the refined candidate kept chosen by FLOP + memory
+    or by the network; each plan's slices/s is measured and
     its whole-network time is n_slices / (slices/s)."""
     import concurrent.futures as cf
 

@@ -89,6 +89,8 @@ SHAPES = [
     (1, 8, 8, 0), (1, 10, 9, 3), (0, 9, 8, 3), (2, 7, 4, 5), (0, 6, 3, 6),
     # whole tiles of the large kernels (bounds-free loop, ordered write-out)
     (1, 9, 8, 5), (0, 10, 7, 6), (2, 8, 7, 7),
+    # more tiles than resident blocks: the persistent 4 x 2 tile loops
+    (1, 14, 9, 5), (1, 14, 9, 3),
 ]
 
 
