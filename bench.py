@@ -30,7 +30,7 @@ KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big<4,2,2,1,32,0>"
                 8: "gett_mfma_big<4,2,2,1,32,1>", 9: "gett_mfma_big<4,4,1,2,32,1>",
                 10: "gett_mfma_big<4,4,1,1,32,1>"}
 # planner settings per workload (search effort, not inputs)
-PLAN_OPTS = {"rqc53": {"sa_iters": 4_000_000}}
+PLAN_OPTS = {"rqc53": {"sa_iters": 4_000_000, "restarts": 8}}
 
 
 def source_hash():

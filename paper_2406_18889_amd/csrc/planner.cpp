@@ -20,11 +20,15 @@
 //   permutation is materialised; the result is written through per-bit
 //   strides into the layout its consumer chose.
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <limits>
 #include <numeric>
 #include <random>
+#include <stdexcept>
+#include <string>
+#include <thread>
 
 #include "plan.h"
 
@@ -638,15 +642,19 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
   }
   if (top.empty()) return "no tree found";
 
-  Candidate best;
-  best.sl = Bits(C.nidx);
-  double best_rank = std::numeric_limits<double>::infinity();
-  std::string first_err;
-  for (int r = 0; r < int(top.size()); ++r) {
-  Candidate cand = std::move(top[r]);
+  // each refinement (annealing and slicing of one candidate, seeded by its
+  // rank) is independent: run them on host threads, then keep the best by
+  // the ranking cost (ties to the lower rank, so the result does not depend
+  // on thread timing)
+  const int nc = int(top.size());
+  std::vector<std::string> errs(nc);
+  std::vector<double> ranks(nc, std::numeric_limits<double>::infinity());
+  auto refine = [&](int r) {
   const uint64_t rseed = opt.seed + 1000003ULL * uint64_t(r);
-  std::string err = [&]() -> std::string {
-  Candidate& best = cand;
+  std::string err;
+  try {
+  err = [&]() -> std::string {
+  Candidate& best = top[r];
   // 2. anneal the candidate tree (half of the budget), with the forced slices
   const long sa_half = std::max(0L, opt.sa_iters / 2);
   auto current = [&]() {
@@ -723,17 +731,39 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
   if (fin.max_w > cap) return "no tree fits the memory cap with the slices allowed";
   return std::string();
   }();
-  if (!err.empty()) {
-    if (first_err.empty()) first_err = err;
-    continue;
+  } catch (const std::exception& ex) {
+    err = std::string("planner refinement failed: ") + ex.what();
   }
-  // rank the complete candidate (tree and slicing) by the ranking cost
-  Score rk = score(C, cand.tree, cand.e, cand.sl, int(cand.order.size()), rank_cf, opt.search_dtype,
-                   opt.chalf_min_log2);
-  if (rk.total < best_rank) {
-    best_rank = rk.total;
-    best = std::move(cand);
+  errs[r] = err;
+  if (err.empty())
+    ranks[r] = score(C, top[r].tree, top[r].e, top[r].sl, int(top[r].order.size()), rank_cf,
+                     opt.search_dtype, opt.chalf_min_log2).total;
+  };
+  const int nthreads = std::max(1, std::min(nc, int(std::thread::hardware_concurrency())));
+  if (nthreads == 1) {
+    for (int r = 0; r < nc; ++r) refine(r);
+  } else {
+    std::atomic<int> next{0};
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nthreads; ++t)
+      pool.emplace_back([&]() {
+        for (int r = next++; r < nc; r = next++) refine(r);
+      });
+    for (auto& th : pool) th.join();
   }
+  Candidate best;
+  best.sl = Bits(C.nidx);
+  double best_rank = std::numeric_limits<double>::infinity();
+  std::string first_err;
+  for (int r = 0; r < nc; ++r) {
+    if (!errs[r].empty()) {
+      if (first_err.empty()) first_err = errs[r];
+      continue;
+    }
+    if (ranks[r] < best_rank) {
+      best_rank = ranks[r];
+      best = std::move(top[r]);
+    }
   }
   if (!std::isfinite(best_rank)) return first_err.empty() ? "no tree found" : first_err;
   Score fin = score(C, best.tree, best.e, best.sl, int(best.order.size()), cf, opt.search_dtype,
