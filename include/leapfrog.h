@@ -275,7 +275,10 @@ lf_status lf_plan_kernel_times(lf_plan* plan, double* total_ms, int64_t* launche
  * (complex-half), 6 the 256 x 128 tile with 64-deep K steps (complex-half),
  * 7 MFMA on 32-row groups against a B of 2^nn <= 16 rows held in registers
  * (complex-half A, 2 <= nk <= 6), 8, 9 and 10 kernels 2, 5 and 4 with tiles
- * dealt to the XCDs in contiguous groups, -1 the default choice; a kernel that does
+ * dealt to the XCDs in contiguous groups, 11 the 256 x 128 tile on eight
+ * waves with operands loaded straight into a three-stage LDS ring
+ * (complex-half, 2^nm a multiple of 256, 2^nn of 128, 5 <= nk <= 21), 12
+ * kernel 11 with the XCD-grouped tile order, -1 the default choice; a kernel that does
  * not apply to the
  * shape or dtype falls back to 0.  Device pointers owned by the caller; A and
  * B 16-byte aligned.  Limits: nz <= 20, nm, nn <= 40.  Errors:

@@ -48,11 +48,15 @@ struct GettArgs {
 // K_SKINNY: MFMA on 32-row groups of A against a B' of at most 32 rows held
 // in registers (N <= 16, 4 <= K <= 64), complex-half A, B either type.
 // K_MFMA_BIG_X, K_MFMA_DB_X, K_MFMA_WIDE_X: kernels 2, 5 and 4 with the XCD-grouped tile order
+// K_MFMA_DMA: the 256 x 128 tile with eight waves and operands loaded straight
+// into a three-stage LDS ring, whole tiles only, complex-half only;
+// K_MFMA_DMA_X: the same with the XCD-grouped tile order
 // (each XCD a contiguous range of tiles, groups of 8 m-tiles sweeping n):
 // less HBM traffic when an A panel would otherwise be fetched by every XCD.
 enum KernelId : int {
   K_THIN = 0, K_MFMA = 1, K_MFMA_BIG = 2, K_NARROW = 3, K_MFMA_WIDE = 4, K_MFMA_DB = 5, K_MFMA_DEEP = 6,
-  K_SKINNY = 7, K_MFMA_BIG_X = 8, K_MFMA_DB_X = 9, K_MFMA_WIDE_X = 10, K_COUNT = 11
+  K_SKINNY = 7, K_MFMA_BIG_X = 8, K_MFMA_DB_X = 9, K_MFMA_WIDE_X = 10, K_MFMA_DMA = 11,
+  K_MFMA_DMA_X = 12, K_COUNT = 13
 };
 
 // a_dt, b_dt, out_dt: 0 complex64 (float pairs), 1 complex-half (_Float16

@@ -778,6 +778,246 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
   block_amax_sat(lmax, lsat, a.amax, a.sat);
 }
 
+// ------------------------------------------------------------ DMA-fed MFMA
+// The 256 x 128 complex tile of the large kernels (256 x 256 real: rows of A
+// by rows of B'), run by eight waves (two per SIMD, 128 m x 64 n' each, the
+// accumulators in 128 VGPRs) so that one wave's MFMAs cover the other's LDS
+// waits.  Whole tiles only (M % 256, N % 128, K % 32 == 0, chosen on the
+// host).  The operand tiles reach LDS without passing through registers:
+// each global->LDS load writes 64 lanes x 16 B = 1 KB at the LDS address held
+// in M0, three stages deep (tile t+2 is requested while tile t is
+// multiplied; one barrier per K step).  Rows are not padded (the 1 KB lands
+// contiguously); chunk c (16 B) of row r sits at slot c ^ ((r >> 1) & 7),
+// which keeps the 16 lanes of each 16-byte fragment read on distinct banks.
+// The loads are issued from inline assembly: the compiler's own form of
+// this load makes it wait for every outstanding load before any LDS access.
+// Here the waits are explicit: before tile t is read, each wave waits until
+// at most one stage of its own loads (tile t+1) is in flight, then all waves
+// meet at the barrier.
+constexpr int DMA_BM = 256, DMA_BN = 128, DMA_BK = 32, DMA_NT = 512;
+constexpr int DMA_SA = DMA_BM * 128;                  // bytes of the A tile of a stage
+constexpr int DMA_STAGE = (DMA_BM + DMA_BN) * 128;    // bytes per stage
+constexpr int DMA_LOADS = (DMA_BM + DMA_BN) * 128 / 1024 / (DMA_NT / 64);   // per wave per stage
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// one 1 KB global->LDS load: lane L's 16 B from sbase + voff go to LDS
+// address m0 + 16 L (sbase and m0 wave-uniform)
+__device__ __forceinline__ void dma_load16(uint32_t voff, const void* sbase, uint32_t m0) {
+  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(sbase), "{m0}"(m0) : "memory");
+}
+
+__device__ __forceinline__ f16x8 bprime_vec(u32x4 raw, const BPrime& bp) {
+  u32x4 w;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = __builtin_amdgcn_perm(raw[i], raw[i], bp.sel) ^ bp.xm;
+  return __builtin_bit_cast(f16x8, w);
+}
+
+template <typename TO, int ORDER>
+__global__ void __launch_bounds__(DMA_NT, 1) gett_mfma_dma(GettArgs a) {
+  constexpr int WM = 4, WN = 2;   // 32 x 32 MFMA tiles per wave in m and n'
+  constexpr int A_LOADS = DMA_BM * 128 / 1024 / (DMA_NT / 64), B_LOADS = DMA_LOADS - A_LOADS;
+  static_assert(A_LOADS == 4 && B_LOADS == 2, "loads per wave");
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[3 * DMA_STAGE];
+  __shared__ int64_t cmT[DMA_BM];
+  __shared__ int64_t cnT[DMA_BN];
+
+  const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
+  const int64_t mt = M / DMA_BM, nt = N / DMA_BN;
+  int64_t z, tm, tn;
+  big_tile_of(blockIdx.x, gridDim.x, ORDER, mt, nt, z, tm, tn);
+  const int64_t m0 = tm * DMA_BM, n0 = tn * DMA_BN;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = w & 1, wn = w >> 1;
+  for (int i = tid; i < DMA_BM; i += DMA_NT) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
+  for (int i = tid; i < DMA_BN; i += DMA_NT) cnT[i] = scatter_bits(n0 + i, a.cn, a.nn);
+  const int64_t czv = scatter_bits(z, a.cz, a.nz);
+  const unsigned char* Ab =
+      static_cast<const unsigned char*>(a.A) + 4 * ((a.offA ? a.offA[z] : z * M * K) + m0 * K);
+  const unsigned char* Bb =
+      static_cast<const unsigned char*>(a.B) + 4 * ((a.offB ? a.offB[z] : z * N * K) + n0 * K);
+
+  // load i of this wave covers rows 8 (wave's first load + i) .. +7; lane L
+  // fills slot L % 8 of row L / 8 of them, i.e. fetches chunk slot ^ swizzle
+  uint32_t voA[A_LOADS], voB[B_LOADS];
+#pragma unroll
+  for (int i = 0; i < A_LOADS; ++i) {
+    const int row = (w * A_LOADS + i) * 8 + (lane >> 3), c = (lane & 7) ^ ((row >> 1) & 7);
+    voA[i] = uint32_t(row) * uint32_t(K) * 4u + uint32_t(c) * 16u;
+  }
+#pragma unroll
+  for (int i = 0; i < B_LOADS; ++i) {
+    const int row = (w * B_LOADS + i) * 8 + (lane >> 3), c = (lane & 7) ^ ((row >> 1) & 7);
+    voB[i] = uint32_t(row) * uint32_t(K) * 4u + uint32_t(c) * 16u;
+  }
+  const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_void_ptr)smem));
+  auto issue = [&](int st, int64_t t) __attribute__((always_inline)) {
+    const unsigned char* ga = Ab + t * (DMA_BK * 4);
+    const unsigned char* gb = Bb + t * (DMA_BK * 4);
+    const uint32_t base = lds0 + uint32_t(st) * DMA_STAGE;
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) dma_load16(voA[i], ga, base + uint32_t(w * A_LOADS + i) * 1024u);
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i)
+      dma_load16(voB[i], gb, base + DMA_SA + uint32_t(w * B_LOADS + i) * 1024u);
+  };
+
+  const BPrime bp(lane & 1);   // parity of the B' row n' of this lane
+  int offA[WM], swA[WM], offB[WN], swB[WN];
+#pragma unroll
+  for (int bm = 0; bm < WM; ++bm) {
+    const int r = wm * 32 * WM + bm * 32 + (lane & 31);
+    offA[bm] = r * 128;
+    swA[bm] = (r >> 1) & 7;
+  }
+#pragma unroll
+  for (int bn = 0; bn < WN; ++bn) {
+    const int r = (wn * 32 * WN + bn * 32 + (lane & 31)) >> 1;
+    offB[bn] = DMA_SA + r * 128;
+    swB[bn] = (r >> 1) & 7;
+  }
+  f16x8 af[2][WM];
+  u32x4 rb[2][WN];
+  auto frags = [&](const unsigned char* s, int kk, int sl) __attribute__((always_inline)) {
+    const int c = (kk >> 2) + (lane >> 5);   // 16 B chunk: 4 complex
+#pragma unroll
+    for (int bm = 0; bm < WM; ++bm) af[sl][bm] = *reinterpret_cast<const f16x8*>(s + offA[bm] + ((c ^ swA[bm]) << 4));
+#pragma unroll
+    for (int bn = 0; bn < WN; ++bn) rb[sl][bn] = *reinterpret_cast<const u32x4*>(s + offB[bn] + ((c ^ swB[bn]) << 4));
+  };
+  f32x16 acc[WN][WM];
+#pragma unroll
+  for (int i = 0; i < WN; ++i)
+#pragma unroll
+    for (int j = 0; j < WM; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+  // k step kk of the tile in s: fragments of step kk+8 are read first
+  auto kstep = [&](auto KK, const unsigned char* s) __attribute__((always_inline)) {
+    constexpr int kk = decltype(KK)::value;
+    constexpr int cs = (kk >> 3) & 1;
+    if constexpr (kk + 8 < DMA_BK) frags(s, kk + 8, cs ^ 1);
+    f16x8 bf[WN];
+#pragma unroll
+    for (int bn = 0; bn < WN; ++bn) bf[bn] = bprime_vec(rb[cs][bn], bp);
+#pragma unroll
+    for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+      for (int bm = 0; bm < WM; ++bm)
+        acc[bn][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[bn], af[cs][bm], acc[bn][bm], 0, 0, 0);
+  };
+  static_assert(DMA_BK == 32, "four k steps per tile");
+  const int64_t T = K / DMA_BK;
+  issue(0, 0);
+  if (T > 1) issue(1, 1);
+  int st = 0;
+  for (int64_t t = 0; t < T; ++t) {
+    // this wave's loads of tile t are done when only tile t+1's remain;
+    // lgkmcnt(0): every fragment read of tile t-1 has returned before any
+    // wave overwrites its stage
+    if (t + 1 < T) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (t + 2 < T) issue(st == 0 ? 2 : st - 1, t + 2);
+    const unsigned char* s = smem + st * DMA_STAGE;
+    frags(s, 0, 0);
+    kstep(std::integral_constant<int, 0>{}, s);
+    kstep(std::integral_constant<int, 8>{}, s);
+    kstep(std::integral_constant<int, 16>{}, s);
+    kstep(std::integral_constant<int, 24>{}, s);
+    st = st == 2 ? 0 : st + 1;
+  }
+  static_assert(DMA_LOADS == 6, "vmcnt above counts one stage of loads");
+
+  TO* C = static_cast<TO*>(a.C);
+  float lmax = 0.0f;
+  unsigned lsat = 0;
+  if constexpr (std::is_same<TO, _Float16>::value) {
+    // staged write-out in the order of the output's strides (as in the
+    // large kernels): 512 threads, 64 elements each
+    constexpr int BM = DMA_BM, BN = DMA_BN, SROW = BN + 1, LM = 8, LN = 7, LT = LM + LN, LO = 9;
+    constexpr int PER = (BM * BN) / DMA_NT;
+    static_assert(BM * SROW * 4 <= 3 * DMA_STAGE, "staged tile fits the operand stages");
+    uint32_t* stage = reinterpret_cast<uint32_t*>(smem);
+    __shared__ int64_t hiAddr[PER];
+    __shared__ int hiIdx[PER];
+    __syncthreads();   // every wave is done with the operand tiles
+#pragma unroll
+    for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+      for (int bm = 0; bm < WM; ++bm) {
+        const int ml = wm * 32 * WM + bm * 32 + (lane & 31);
+#pragma unroll
+        for (int v = 0; v < 16; v += 2) {
+          const int nl = (wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1;
+          float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
+          lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+          if (!(fabsf(re) <= HALF_MAX)) { lsat += a.amax_only ? 0 : 1; re = (re != re) ? 0.0f : copysignf(HALF_MAX, re); }
+          if (!(fabsf(im) <= HALF_MAX)) { lsat += a.amax_only ? 0 : 1; im = (im != im) ? 0.0f : copysignf(HALF_MAX, im); }
+          f16x2 h;
+          h[0] = (_Float16)re;
+          h[1] = (_Float16)im;
+          uint32_t wv;
+          __builtin_memcpy(&wv, &h, 4);
+          stage[ml * SROW + nl] = wv;
+        }
+      }
+    int64_t stv[LT];
+    int bit[LT];
+#pragma unroll
+    for (int i = 0; i < LT; ++i) {
+      bit[i] = i;
+      stv[i] = i < LM ? a.cm[i] : a.cn[i - LM];
+    }
+    for (int i = 1; i < LT; ++i)
+      for (int j = i; j > 0 && stv[j] < stv[j - 1]; --j) {
+        const int64_t ts = stv[j]; stv[j] = stv[j - 1]; stv[j - 1] = ts;
+        const int tb = bit[j]; bit[j] = bit[j - 1]; bit[j - 1] = tb;
+      }
+    // element e = tid + 512 j: its low 9 bits come from tid, the rest from j
+    auto split = [&](int e, int lo, int hi, int64_t& addr, int& idx) {
+      addr = 0;
+      int ml = 0, nl = 0;
+      for (int i = lo; i < hi; ++i)
+        if ((e >> (i - lo)) & 1) {
+          addr += stv[i];
+          if (bit[i] < LM) ml |= 1 << bit[i];
+          else nl |= 1 << (bit[i] - LM);
+        }
+      idx = ml * SROW + nl;
+    };
+    int64_t loAddr;
+    int loIdx;
+    split(tid, 0, LO, loAddr, loIdx);
+    if (tid < PER) split(tid, LO, LT, hiAddr[tid], hiIdx[tid]);
+    __syncthreads();
+    if (!a.amax_only) {
+      const int64_t base = czv + cmT[0] + cnT[0] + loAddr;
+      uint32_t* Cw = reinterpret_cast<uint32_t*>(C);
+#pragma unroll 8
+      for (int j = 0; j < PER; ++j) Cw[base + hiAddr[j]] = stage[loIdx + hiIdx[j]];
+    }
+  } else {
+#pragma unroll
+    for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+      for (int bm = 0; bm < WM; ++bm) {
+        const int ml = wm * 32 * WM + bm * 32 + (lane & 31);
+        const int64_t cb = czv + cmT[ml];
+#pragma unroll
+        for (int v = 0; v < 16; v += 2) {
+          const int nl = (wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1;
+          const float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
+          lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+          if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
+        }
+      }
+  }
+  block_amax_sat(lmax, lsat, a.amax, a.sat);
+}
+
 // ------------------------------------------------------------ skinny MFMA
 // Steps with a short side: N <= 16 complex (at most 32 rows of B'),
 // 4 <= K <= 64, complex-half A, M >= 32 GPW.  Each wave multiplies 32 rows of
@@ -921,6 +1161,9 @@ bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
   if (kernel == K_MFMA_DB || kernel == K_MFMA_DEEP) return in_dt == 1 && nm >= 7 && nn >= 6;
   if (kernel == K_NARROW) return nm >= 8 && nk <= 6 && nn <= 8 && nn + nk <= 8;
   if (kernel == K_SKINNY) return in_dt == 1 && nn <= 4 && nk >= 2 && nk <= 6 && nm >= (nk == 6 ? 6 : 7);
+  // whole 256 x 128 tiles, K a multiple of 32, and per-lane load offsets
+  // (row * K * 4 bytes within a 256-row panel) that fit 32 bits
+  if (kernel == K_MFMA_DMA || kernel == K_MFMA_DMA_X) return in_dt == 1 && nm >= 8 && nn >= 7 && nk >= 5 && nk <= 21;
   return false;
 }
 
@@ -949,6 +1192,15 @@ static hipError_t launch_big(const GettArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename TO, int ORDER>
+static hipError_t launch_dma(const GettArgs& a, hipStream_t s) {
+  if (a.nm < 8 || a.nn < 7 || a.nk < 5 || a.nk > 21) return hipErrorInvalidValue;
+  const int64_t blocks = (int64_t(1) << a.nz) * ((int64_t(1) << a.nm) / DMA_BM) * ((int64_t(1) << a.nn) / DMA_BN);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gett_mfma_dma<TO, ORDER>), dim3(unsigned(blocks)), dim3(DMA_NT), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename TI, typename TO>
 static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
   if (kernel == K_THIN) return launch_thin<TI, TI, TO>(a, s);
@@ -963,6 +1215,8 @@ static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((gett_mfma<TI, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
   } else {
     if constexpr (std::is_same<TI, _Float16>::value) {
+      if (kernel == K_MFMA_DMA) return launch_dma<TO, 0>(a, s);
+      if (kernel == K_MFMA_DMA_X) return launch_dma<TO, 1>(a, s);
       if (kernel == K_MFMA_BIG_X) return launch_big<TO, 4, 2, 2, 1, 32, 1>(a, s);
       if (kernel == K_MFMA_DB_X) return launch_big<TO, 4, 4, 1, 2, 32, 1>(a, s);
       if (kernel == K_MFMA_WIDE_X) return launch_big<TO, 4, 4, 1, 1, 32, 1>(a, s);

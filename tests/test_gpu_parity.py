@@ -89,6 +89,8 @@ SHAPES = [
     (1, 8, 8, 0), (1, 10, 9, 3), (0, 9, 8, 3), (2, 7, 4, 5), (0, 6, 3, 6),
     # whole tiles of the large kernels (bounds-free loop, ordered write-out)
     (1, 9, 8, 5), (0, 10, 7, 6), (2, 8, 7, 7),
+    # whole tiles, long K: the three-stage LDS ring wraps several times
+    (0, 8, 7, 8), (0, 9, 7, 10),
     # more tiles than resident blocks: the persistent 4 x 2 tile loops
     (1, 14, 9, 5), (1, 14, 9, 3),
 ]
@@ -106,6 +108,8 @@ def _applicable(kernel, dt, shape):
         return dt == "chalf" and nm >= 7 and nn >= 6
     if kernel == 7:
         return dt == "chalf" and nn <= 4 and 2 <= nk <= 6 and nm >= (6 if nk == 6 else 7)
+    if kernel in (11, 12):
+        return dt == "chalf" and nm >= 8 and nn >= 7 and 5 <= nk <= 21
     return True
 
 
@@ -133,7 +137,7 @@ def _to_half_pairs(x, e):
     return torch.from_numpy(v.astype(np.float16)).cuda()
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_pair_chalf(lf, kernel, shape):
     nz, nm, nn, nk = shape
@@ -182,14 +186,16 @@ def test_pair_mixed_half_a_c64_b(lf, kernel, shape):
     assert rel_err(dC.cpu().numpy(), ref) < C64_TOL
 
 
-def test_pair_half_in_c64_out(lf):
-    nz, nm, nn, nk = 0, 7, 5, 6
-    A = wl.random_complex((1 << (nm + nk),), seed=21)
-    B = wl.random_complex((1 << (nn + nk),), seed=22)
+@pytest.mark.parametrize("kernel,shape", [(1, (0, 7, 5, 6)), (11, (0, 8, 7, 6)), (12, (1, 8, 7, 5))])
+def test_pair_half_in_c64_out(lf, kernel, shape):
+    nz, nm, nn, nk = shape
+    _say(f"pair half in, c64 out kernel={kernel} shape={shape}")
+    A = wl.random_complex((1 << (nz + nm + nk),), seed=21)
+    B = wl.random_complex((1 << (nz + nn + nk),), seed=22)
     st = _rand_strides(nz, nm, nn, seed=23)
     dA, dB = _to_half_pairs(A, 0), _to_half_pairs(B, 0)
-    dC = torch.zeros(1 << (nm + nn), dtype=torch.complex64, device="cuda")
-    lf.contract_pair(dA, dB, dC, nz, nm, nn, nk, st, 1.0, 1)
+    dC = torch.zeros(1 << (nz + nm + nn), dtype=torch.complex64, device="cuda")
+    lf.contract_pair(dA, dB, dC, nz, nm, nn, nk, st, 1.0, kernel)
     torch.cuda.synchronize()
     Ah = dA.cpu().numpy().astype(np.float64) @ np.array([1, 1j])
     Bh = dB.cpu().numpy().astype(np.float64) @ np.array([1, 1j])
