@@ -779,25 +779,24 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
 }
 
 // ------------------------------------------------------------ DMA-fed MFMA
-// The 256 x 128 complex tile of the large kernels (256 x 256 real: rows of A
-// by rows of B'), run by eight waves (two per SIMD, 128 m x 64 n' each, the
-// accumulators in 128 VGPRs) so that one wave's MFMAs cover the other's LDS
-// waits.  Whole tiles only (M % 256, N % 128, K % 32 == 0, chosen on the
-// host).  The operand tiles reach LDS without passing through registers:
-// each global->LDS load writes 64 lanes x 16 B = 1 KB at the LDS address held
-// in M0, three stages deep (tile t+2 is requested while tile t is
-// multiplied; one barrier per K step).  Rows are not padded (the 1 KB lands
-// contiguously); chunk c (16 B) of row r sits at slot c ^ ((r >> 1) & 7),
-// which keeps the 16 lanes of each 16-byte fragment read on distinct banks.
-// The loads are issued from inline assembly: the compiler's own form of
-// this load makes it wait for every outstanding load before any LDS access.
-// Here the waits are explicit: before tile t is read, each wave waits until
-// at most one stage of its own loads (tile t+1) is in flight, then all waves
-// meet at the barrier.
-constexpr int DMA_BM = 256, DMA_BN = 128, DMA_BK = 32, DMA_NT = 512;
+// The 256 m x 128 n complex tile, run by eight waves (two per SIMD, each
+// 64 m x 64 n, the accumulators in 128 VGPRs) so that one wave's MFMAs cover
+// the other's LDS waits.  The real and imaginary parts of C are separate
+// 32 x 32 MFMA blocks that share the A fragment: each lane reads one whole
+// B row chunk, and both operand forms of it, (Br, -Bi) and (Bi, Br), are
+// made in registers (one operation per 32-bit word), so no two lanes read
+// the same LDS bytes.  Whole tiles only (M % 256, N % 128, K % 32 == 0,
+// chosen on the host).  The operand tiles reach LDS without passing through
+// registers: each global->LDS load writes 64 lanes x 16 B = 1 KB at the LDS
+// address held in M0, three stages deep.  Rows are not padded (the 1 KB
+// lands contiguously); chunk c (16 B) of row r sits at slot c ^ ((r >> 1) & 7),
+// which keeps each fragment read free of bank conflicts.  The loads are
+// issued from inline assembly: the compiler's own form of this load makes it
+// wait for every outstanding load before any LDS access.  Here the waits are
+// explicit (see the main loop).
+constexpr int DMA_BM = 256, DMA_BN = 128, DMA_BK = 32;
 constexpr int DMA_SA = DMA_BM * 128;                  // bytes of the A tile of a stage
 constexpr int DMA_STAGE = (DMA_BM + DMA_BN) * 128;    // bytes per stage
-constexpr int DMA_LOADS = (DMA_BM + DMA_BN) * 128 / 1024 / (DMA_NT / 64);   // per wave per stage
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -808,18 +807,24 @@ __device__ __forceinline__ void dma_load16(uint32_t voff, const void* sbase, uin
   asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(sbase), "{m0}"(m0) : "memory");
 }
 
-__device__ __forceinline__ f16x8 bprime_vec(u32x4 raw, const BPrime& bp) {
-  u32x4 w;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) w[i] = __builtin_amdgcn_perm(raw[i], raw[i], bp.sel) ^ bp.xm;
-  return __builtin_bit_cast(f16x8, w);
+// s_waitcnt vmcnt(N) lgkmcnt(0), then s_barrier (N: this wave's loads that
+// may still be in flight)
+template <int N>
+__device__ __forceinline__ void wait_loads_barrier() {
+  static_assert(N == 0 || N == 6 || N == 12, "vmcnt immediate");
+  if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 6) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 12) asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 template <typename TO, int ORDER>
-__global__ void __launch_bounds__(DMA_NT, 1) gett_mfma_dma(GettArgs a) {
-  constexpr int WM = 4, WN = 2;   // 32 x 32 MFMA tiles per wave in m and n'
-  constexpr int A_LOADS = DMA_BM * 128 / 1024 / (DMA_NT / 64), B_LOADS = DMA_LOADS - A_LOADS;
-  static_assert(A_LOADS == 4 && B_LOADS == 2, "loads per wave");
+__global__ void __launch_bounds__(512, 1) gett_mfma_dma(GettArgs a) {
+  constexpr int NW = 8, NT = 64 * NW;
+  constexpr int WM = 2, WN = 2;                  // 32 x 32 MFMA tiles per wave in m and complex n
+  constexpr int MW = DMA_BM / (32 * WM);         // waves along m
+  constexpr int A_LOADS = DMA_BM * 128 / 1024 / NW, B_LOADS = DMA_BN * 128 / 1024 / NW;
+  constexpr int LOADS = A_LOADS + B_LOADS;       // per wave per stage
+  static_assert(MW * 2 == NW && LOADS * NW * 1024 == DMA_STAGE, "wave grid and loads");
   __shared__ __attribute__((aligned(1024))) unsigned char smem[3 * DMA_STAGE];
   __shared__ int64_t cmT[DMA_BM];
   __shared__ int64_t cnT[DMA_BN];
@@ -831,9 +836,9 @@ __global__ void __launch_bounds__(DMA_NT, 1) gett_mfma_dma(GettArgs a) {
   const int64_t m0 = tm * DMA_BM, n0 = tn * DMA_BN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = w & 1, wn = w >> 1;
-  for (int i = tid; i < DMA_BM; i += DMA_NT) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
-  for (int i = tid; i < DMA_BN; i += DMA_NT) cnT[i] = scatter_bits(n0 + i, a.cn, a.nn);
+  const int wm = w % MW, wn = w / MW;
+  for (int i = tid; i < DMA_BM; i += NT) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
+  for (int i = tid; i < DMA_BN; i += NT) cnT[i] = scatter_bits(n0 + i, a.cn, a.nn);
   const int64_t czv = scatter_bits(z, a.cz, a.nz);
   const unsigned char* Ab =
       static_cast<const unsigned char*>(a.A) + 4 * ((a.offA ? a.offA[z] : z * M * K) + m0 * K);
@@ -865,7 +870,6 @@ __global__ void __launch_bounds__(DMA_NT, 1) gett_mfma_dma(GettArgs a) {
       dma_load16(voB[i], gb, base + DMA_SA + uint32_t(w * B_LOADS + i) * 1024u);
   };
 
-  const BPrime bp(lane & 1);   // parity of the B' row n' of this lane
   int offA[WM], swA[WM], offB[WN], swB[WN];
 #pragma unroll
   for (int bm = 0; bm < WM; ++bm) {
@@ -875,7 +879,7 @@ __global__ void __launch_bounds__(DMA_NT, 1) gett_mfma_dma(GettArgs a) {
   }
 #pragma unroll
   for (int bn = 0; bn < WN; ++bn) {
-    const int r = (wn * 32 * WN + bn * 32 + (lane & 31)) >> 1;
+    const int r = wn * 32 * WN + bn * 32 + (lane & 31);
     offB[bn] = DMA_SA + r * 128;
     swB[bn] = (r >> 1) & 7;
   }
@@ -888,57 +892,116 @@ __global__ void __launch_bounds__(DMA_NT, 1) gett_mfma_dma(GettArgs a) {
 #pragma unroll
     for (int bn = 0; bn < WN; ++bn) rb[sl][bn] = *reinterpret_cast<const u32x4*>(s + offB[bn] + ((c ^ swB[bn]) << 4));
   };
-  f32x16 acc[WN][WM];
+  // acc[bn][0][bm]: real parts, acc[bn][1][bm]: imaginary parts of the
+  // 32 n x 32 m block (bn, bm)
+  f32x16 acc[WN][2][WM];
 #pragma unroll
   for (int i = 0; i < WN; ++i)
 #pragma unroll
-    for (int j = 0; j < WM; ++j)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-  // k step kk of the tile in s: fragments of step kk+8 are read first
-  auto kstep = [&](auto KK, const unsigned char* s) __attribute__((always_inline)) {
-    constexpr int kk = decltype(KK)::value;
-    constexpr int cs = (kk >> 3) & 1;
-    if constexpr (kk + 8 < DMA_BK) frags(s, kk + 8, cs ^ 1);
-    f16x8 bf[WN];
+      for (int j = 0; j < WM; ++j)
 #pragma unroll
-    for (int bn = 0; bn < WN; ++bn) bf[bn] = bprime_vec(rb[cs][bn], bp);
+        for (int v = 0; v < 16; ++v) acc[i][p][j][v] = 0.0f;
+  // the matrix part of a k step.  With A's rows as (re, im) pairs along k,
+  // Re C[n, m] = sum_k A[m, k] . (Br, -Bi)[n, k] and
+  // Im C[n, m] = sum_k A[m, k] . (Bi, Br)[n, k]: one B row read from LDS
+  // gives both operand rows, by a sign flip of the high half and by a swap
+  // of the halves of each 32-bit word.  Then 8 MFMAs.
+  auto bprime = [&](auto CS, f16x8 (*bf)[2]) __attribute__((always_inline)) {
+    constexpr int cs = decltype(CS)::value;
+#pragma unroll
+    for (int bn = 0; bn < WN; ++bn) {
+      u32x4 re, im;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t x = rb[cs][bn][i];
+        re[i] = x ^ 0x80000000u;
+        im[i] = __builtin_amdgcn_alignbit(x, x, 16);
+      }
+      bf[bn][0] = __builtin_bit_cast(f16x8, re);
+      bf[bn][1] = __builtin_bit_cast(f16x8, im);
+    }
+  };
+  auto mma = [&](auto CS, f16x8 (*bf)[2]) __attribute__((always_inline)) {
+    constexpr int cs = decltype(CS)::value;
 #pragma unroll
     for (int bn = 0; bn < WN; ++bn)
 #pragma unroll
-      for (int bm = 0; bm < WM; ++bm)
-        acc[bn][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[bn], af[cs][bm], acc[bn][bm], 0, 0, 0);
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int bm = 0; bm < WM; ++bm)
+          acc[bn][p][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[bn][p], af[cs][bm], acc[bn][p][bm], 0, 0, 0);
+  };
+  auto mfmas = [&](auto CS) __attribute__((always_inline)) {
+    f16x8 bf[WN][2];
+    bprime(CS, bf);
+    mma(CS, bf);
   };
   static_assert(DMA_BK == 32, "four k steps per tile");
+  // Pipeline: the fragments of k step j+1 are read (into the other register
+  // set) before the MFMAs of step j are issued, and the scheduling fences
+  // keep the compiler from sinking those reads to their use.  Tile t+3 is
+  // requested into the stage of tile t once every wave has passed the
+  // barrier in the last k step of tile t (by then all fragments of tile t
+  // are in registers), so the barrier falls between MFMAs of the same tile
+  // and each load has two tiles of compute to arrive.
   const int64_t T = K / DMA_BK;
   issue(0, 0);
   if (T > 1) issue(1, 1);
+  if (T > 2) issue(2, 2);
+  if (T > 2) wait_loads_barrier<2 * LOADS>();
+  else if (T > 1) wait_loads_barrier<LOADS>();
+  else wait_loads_barrier<0>();
+  frags(smem, 0, 0);
   int st = 0;
   for (int64_t t = 0; t < T; ++t) {
-    // this wave's loads of tile t are done when only tile t+1's remain;
-    // lgkmcnt(0): every fragment read of tile t-1 has returned before any
-    // wave overwrites its stage
-    if (t + 1 < T) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    if (t + 2 < T) issue(st == 0 ? 2 : st - 1, t + 2);
     const unsigned char* s = smem + st * DMA_STAGE;
-    frags(s, 0, 0);
-    kstep(std::integral_constant<int, 0>{}, s);
-    kstep(std::integral_constant<int, 8>{}, s);
-    kstep(std::integral_constant<int, 16>{}, s);
-    kstep(std::integral_constant<int, 24>{}, s);
-    st = st == 2 ? 0 : st + 1;
+    const int nst = st == 2 ? 0 : st + 1;
+    frags(s, 8, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mfmas(std::integral_constant<int, 0>{});
+    __builtin_amdgcn_sched_barrier(0);
+    frags(s, 16, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    mfmas(std::integral_constant<int, 1>{});
+    __builtin_amdgcn_sched_barrier(0);
+    frags(s, 24, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mfmas(std::integral_constant<int, 0>{});
+    __builtin_amdgcn_sched_barrier(0);
+    // B' of the last k step before the branch: its reads are the newest
+    // ones here, so the MFMAs after the branch need no wait on the reads of
+    // the next tile
+    f16x8 bf3[WN][2];
+    bprime(std::integral_constant<int, 1>{}, bf3);
+#pragma unroll
+    for (int bn = 0; bn < WN; ++bn) asm volatile("" : "+v"(bf3[bn][0]), "+v"(bf3[bn][1]));   // keep it here
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 1 < T) {
+      // tile t+1 has landed (only tile t+2's loads may be in flight) and
+      // every wave's reads of tile t have returned: stage st is free
+      if (t + 2 < T) wait_loads_barrier<LOADS>();
+      else wait_loads_barrier<0>();
+      if (t + 3 < T) issue(st, t + 3);
+      frags(smem + nst * DMA_STAGE, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    mma(std::integral_constant<int, 1>{}, bf3);
+    __builtin_amdgcn_sched_barrier(0);
+    st = nst;
   }
-  static_assert(DMA_LOADS == 6, "vmcnt above counts one stage of loads");
+
 
   TO* C = static_cast<TO*>(a.C);
   float lmax = 0.0f;
   unsigned lsat = 0;
   if constexpr (std::is_same<TO, _Float16>::value) {
     // staged write-out in the order of the output's strides (as in the
-    // large kernels): 512 threads, 64 elements each
-    constexpr int BM = DMA_BM, BN = DMA_BN, SROW = BN + 1, LM = 8, LN = 7, LT = LM + LN, LO = 9;
-    constexpr int PER = (BM * BN) / DMA_NT;
+    // large kernels): NT threads, PER elements each
+    constexpr int BM = DMA_BM, BN = DMA_BN, SROW = BN + 1, LM = 8, LN = 7, LT = LM + LN;
+    constexpr int LO = 9, PER = (BM * BN) / NT;
+    static_assert((1 << LO) == NT && PER <= NT, "thread bits of the write-out");
     static_assert(BM * SROW * 4 <= 3 * DMA_STAGE, "staged tile fits the operand stages");
     uint32_t* stage = reinterpret_cast<uint32_t*>(smem);
     __shared__ int64_t hiAddr[PER];
@@ -950,9 +1013,9 @@ __global__ void __launch_bounds__(DMA_NT, 1) gett_mfma_dma(GettArgs a) {
       for (int bm = 0; bm < WM; ++bm) {
         const int ml = wm * 32 * WM + bm * 32 + (lane & 31);
 #pragma unroll
-        for (int v = 0; v < 16; v += 2) {
-          const int nl = (wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1;
-          float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
+        for (int v = 0; v < 16; ++v) {
+          const int nl = wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          float re = acc[bn][0][bm][v] * a.scale, im = acc[bn][1][bm][v] * a.scale;
           lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
           if (!(fabsf(re) <= HALF_MAX)) { lsat += a.amax_only ? 0 : 1; re = (re != re) ? 0.0f : copysignf(HALF_MAX, re); }
           if (!(fabsf(im) <= HALF_MAX)) { lsat += a.amax_only ? 0 : 1; im = (im != im) ? 0.0f : copysignf(HALF_MAX, im); }
@@ -976,7 +1039,7 @@ __global__ void __launch_bounds__(DMA_NT, 1) gett_mfma_dma(GettArgs a) {
         const int64_t ts = stv[j]; stv[j] = stv[j - 1]; stv[j - 1] = ts;
         const int tb = bit[j]; bit[j] = bit[j - 1]; bit[j - 1] = tb;
       }
-    // element e = tid + 512 j: its low 9 bits come from tid, the rest from j
+    // element e = tid + NT j: its low LO bits come from tid, the rest from j
     auto split = [&](int e, int lo, int hi, int64_t& addr, int& idx) {
       addr = 0;
       int ml = 0, nl = 0;
@@ -1007,9 +1070,9 @@ __global__ void __launch_bounds__(DMA_NT, 1) gett_mfma_dma(GettArgs a) {
         const int ml = wm * 32 * WM + bm * 32 + (lane & 31);
         const int64_t cb = czv + cmT[ml];
 #pragma unroll
-        for (int v = 0; v < 16; v += 2) {
-          const int nl = (wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1;
-          const float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
+        for (int v = 0; v < 16; ++v) {
+          const int nl = wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          const float re = acc[bn][0][bm][v] * a.scale, im = acc[bn][1][bm][v] * a.scale;
           lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
           if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
         }
@@ -1197,7 +1260,7 @@ static hipError_t launch_dma(const GettArgs& a, hipStream_t s) {
   if (a.nm < 8 || a.nn < 7 || a.nk < 5 || a.nk > 21) return hipErrorInvalidValue;
   const int64_t blocks = (int64_t(1) << a.nz) * ((int64_t(1) << a.nm) / DMA_BM) * ((int64_t(1) << a.nn) / DMA_BN);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gett_mfma_dma<TO, ORDER>), dim3(unsigned(blocks)), dim3(DMA_NT), 0, s, a);
+  hipLaunchKernelGGL((gett_mfma_dma<TO, ORDER>), dim3(unsigned(blocks)), dim3(512), 0, s, a);
   return hipGetLastError();
 }
 

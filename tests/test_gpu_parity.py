@@ -186,7 +186,8 @@ def test_pair_mixed_half_a_c64_b(lf, kernel, shape):
     assert rel_err(dC.cpu().numpy(), ref) < C64_TOL
 
 
-@pytest.mark.parametrize("kernel,shape", [(1, (0, 7, 5, 6)), (11, (0, 8, 7, 6)), (12, (1, 8, 7, 5))])
+@pytest.mark.parametrize("kernel,shape", [(1, (0, 7, 5, 6)), (11, (0, 8, 7, 6)), (12, (1, 8, 7, 5)),
+                                          (11, (0, 9, 7, 8)), (12, (1, 8, 8, 5))])
 def test_pair_half_in_c64_out(lf, kernel, shape):
     nz, nm, nn, nk = shape
     _say(f"pair half in, c64 out kernel={kernel} shape={shape}")
