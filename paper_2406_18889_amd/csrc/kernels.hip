@@ -887,10 +887,11 @@ __global__ void __launch_bounds__(512, 1) gett_mfma_dma(GettArgs a) {
   u32x4 rb[2][WN];
   auto frags = [&](const unsigned char* s, int kk, int sl) __attribute__((always_inline)) {
     const int c = (kk >> 2) + (lane >> 5);   // 16 B chunk: 4 complex
-#pragma unroll
-    for (int bm = 0; bm < WM; ++bm) af[sl][bm] = *reinterpret_cast<const f16x8*>(s + offA[bm] + ((c ^ swA[bm]) << 4));
+    // B first: its B' operands are formed before this A set is needed
 #pragma unroll
     for (int bn = 0; bn < WN; ++bn) rb[sl][bn] = *reinterpret_cast<const u32x4*>(s + offB[bn] + ((c ^ swB[bn]) << 4));
+#pragma unroll
+    for (int bm = 0; bm < WM; ++bm) af[sl][bm] = *reinterpret_cast<const f16x8*>(s + offA[bm] + ((c ^ swA[bm]) << 4));
   };
   // acc[bn][0][bm]: real parts, acc[bn][1][bm]: imaginary parts of the
   // 32 n x 32 m block (bn, bm)
@@ -933,15 +934,26 @@ __global__ void __launch_bounds__(512, 1) gett_mfma_dma(GettArgs a) {
         for (int bm = 0; bm < WM; ++bm)
           acc[bn][p][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[bn][p], af[cs][bm], acc[bn][p][bm], 0, 0, 0);
   };
-  auto mfmas = [&](auto CS) __attribute__((always_inline)) {
-    f16x8 bf[WN][2];
-    bprime(CS, bf);
+  // the MFMAs of one k step on A set CS and B' operands bf, with the B' of
+  // the next k step (raw set NCS) formed in between: its 16 VALU operations
+  // are spread over the last five MFMAs, so they run while the matrix pipe
+  // is busy instead of in a gap of their own
+  auto mma_next = [&](auto CS, f16x8 (*bf)[2], auto NCS, f16x8 (*bfn)[2]) __attribute__((always_inline)) {
     mma(CS, bf);
+    bprime(NCS, bfn);
+    __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
   };
   static_assert(DMA_BK == 32, "four k steps per tile");
   // Pipeline: the fragments of k step j+1 are read (into the other register
   // set) before the MFMAs of step j are issued, and the scheduling fences
-  // keep the compiler from sinking those reads to their use.  Tile t+3 is
+  // keep the compiler from sinking those reads to their use; the B' operands
+  // of step j+1 are formed during the MFMAs of step j.  Tile t+3 is
   // requested into the stage of tile t once every wave has passed the
   // barrier in the last k step of tile t (by then all fragments of tile t
   // are in registers), so the barrier falls between MFMAs of the same tile
@@ -954,44 +966,45 @@ __global__ void __launch_bounds__(512, 1) gett_mfma_dma(GettArgs a) {
   else if (T > 1) wait_loads_barrier<LOADS>();
   else wait_loads_barrier<0>();
   frags(smem, 0, 0);
+  f16x8 bfe[WN][2], bfo[WN][2];   // B' operands of even and odd k steps
+  bprime(std::integral_constant<int, 0>{}, bfe);
   int st = 0;
-  for (int64_t t = 0; t < T; ++t) {
-    const unsigned char* s = smem + st * DMA_STAGE;
-    const int nst = st == 2 ? 0 : st + 1;
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  // k steps 0..2 of the tile in s
+  auto three_steps = [&](const unsigned char* s) __attribute__((always_inline)) {
     frags(s, 8, 1);
     __builtin_amdgcn_sched_barrier(0);
-    mfmas(std::integral_constant<int, 0>{});
+    mma_next(I0{}, bfe, I1{}, bfo);
     __builtin_amdgcn_sched_barrier(0);
     frags(s, 16, 0);
     __builtin_amdgcn_sched_barrier(0);
-    mfmas(std::integral_constant<int, 1>{});
+    mma_next(I1{}, bfo, I0{}, bfe);
     __builtin_amdgcn_sched_barrier(0);
     frags(s, 24, 1);
     __builtin_amdgcn_sched_barrier(0);
-    mfmas(std::integral_constant<int, 0>{});
-    __builtin_amdgcn_sched_barrier(0);
-    // B' of the last k step before the branch: its reads are the newest
-    // ones here, so the MFMAs after the branch need no wait on the reads of
-    // the next tile
-    f16x8 bf3[WN][2];
-    bprime(std::integral_constant<int, 1>{}, bf3);
+    mma_next(I0{}, bfe, I1{}, bfo);
 #pragma unroll
-    for (int bn = 0; bn < WN; ++bn) asm volatile("" : "+v"(bf3[bn][0]), "+v"(bf3[bn][1]));   // keep it here
+    for (int bn = 0; bn < WN; ++bn) asm volatile("" : "+v"(bfo[bn][0]), "+v"(bfo[bn][1]));   // formed here
     __builtin_amdgcn_sched_barrier(0);
-    if (t + 1 < T) {
-      // tile t+1 has landed (only tile t+2's loads may be in flight) and
-      // every wave's reads of tile t have returned: stage st is free
-      if (t + 2 < T) wait_loads_barrier<LOADS>();
-      else wait_loads_barrier<0>();
-      if (t + 3 < T) issue(st, t + 3);
-      frags(smem + nst * DMA_STAGE, 0, 0);
-    }
+  };
+  // every tile but the last: its k step 3 overlaps the first reads of the next
+  for (int64_t t = 0; t + 1 < T; ++t) {
+    const int nst = st == 2 ? 0 : st + 1;
+    three_steps(smem + st * DMA_STAGE);
+    // tile t+1 has landed (only tile t+2's loads may be in flight) and
+    // every wave's reads of tile t have returned: stage st is free
+    if (t + 2 < T) wait_loads_barrier<LOADS>();
+    else wait_loads_barrier<0>();
+    if (t + 3 < T) issue(st, t + 3);
+    frags(smem + nst * DMA_STAGE, 0, 0);
     __builtin_amdgcn_sched_barrier(0);
-    mma(std::integral_constant<int, 1>{}, bf3);
+    mma_next(I1{}, bfo, I0{}, bfe);
     __builtin_amdgcn_sched_barrier(0);
     st = nst;
   }
-
+  three_steps(smem + st * DMA_STAGE);
+  mma(I1{}, bfo);
 
   TO* C = static_cast<TO*>(a.C);
   float lmax = 0.0f;
