@@ -28,7 +28,8 @@ KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big<4,2,2,1,32,0>"
                 4: "gett_mfma_big<4,4,1,1,32,0>", 5: "gett_mfma_big<4,4,1,2,32,0>",
                 6: "gett_mfma_big<4,4,1,1,64,0>", 7: "gett_skinny",
                 8: "gett_mfma_big<4,2,2,1,32,1>", 9: "gett_mfma_big<4,4,1,2,32,1>",
-                10: "gett_mfma_big<4,4,1,1,32,1>", 11: "gett_mfma_dma<0>", 12: "gett_mfma_dma<1>"}
+                10: "gett_mfma_big<4,4,1,1,32,1>", 11: "gett_mfma_dma<0,8>", 12: "gett_mfma_dma<1,8>",
+                13: "gett_mfma_dma<0,4>", 14: "gett_mfma_dma<1,4>"}
 # planner settings per workload (search effort, not inputs)
 PLAN_OPTS = {"rqc53": {"sa_iters": 4_000_000, "restarts": 8}}
 

@@ -811,19 +811,28 @@ __device__ __forceinline__ void dma_load16(uint32_t voff, const void* sbase, uin
 // may still be in flight)
 template <int N>
 __device__ __forceinline__ void wait_loads_barrier() {
-  static_assert(N == 0 || N == 6 || N == 12, "vmcnt immediate");
+  static_assert(N == 0 || N == 6 || N == 8 || N == 12 || N == 15, "vmcnt immediate");
   if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   if constexpr (N == 6) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 8) asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   if constexpr (N == 12) asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 15) asm volatile("s_waitcnt vmcnt(15) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-template <typename TO, int ORDER>
-__global__ void __launch_bounds__(512, 1) gett_mfma_dma(GettArgs a) {
-  constexpr int NW = 8, NT = 64 * NW;
-  constexpr int WM = 2, WN = 2;                  // 32 x 32 MFMA tiles per wave in m and complex n
+// NW = 8: eight waves (two per SIMD), each 64 m x 64 n, 8 MFMAs per k step,
+// 128 accumulator registers.  NW = 4: four waves (one per SIMD), each 128 m x
+// 64 n, 16 MFMAs per k step, 256 accumulator registers (AGPRs): fewer LDS
+// bytes and VALU operations per MFMA, and the waits must be hidden by the
+// order of one wave's instructions alone.
+template <typename TO, int ORDER, int NW>
+__global__ void __launch_bounds__(64 * NW, 1) gett_mfma_dma(GettArgs a) {
+  static_assert(NW == 4 || NW == 8, "wave count");
+  constexpr int NT = 64 * NW;
+  constexpr int WM = NW == 8 ? 2 : 4, WN = 2;   // 32 x 32 MFMA tiles per wave in m and complex n
   constexpr int MW = DMA_BM / (32 * WM);         // waves along m
   constexpr int A_LOADS = DMA_BM * 128 / 1024 / NW, B_LOADS = DMA_BN * 128 / 1024 / NW;
   constexpr int LOADS = A_LOADS + B_LOADS;       // per wave per stage
+  constexpr int CHUNK = (LOADS + 3) / 4;         // loads of a tile issued per k step
   static_assert(MW * 2 == NW && LOADS * NW * 1024 == DMA_STAGE, "wave grid and loads");
   __shared__ __attribute__((aligned(1024))) unsigned char smem[3 * DMA_STAGE];
   __shared__ int64_t cmT[DMA_BM];
@@ -859,16 +868,25 @@ __global__ void __launch_bounds__(512, 1) gett_mfma_dma(GettArgs a) {
     voB[i] = uint32_t(row) * uint32_t(K) * 4u + uint32_t(c) * 16u;
   }
   const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_void_ptr)smem));
-  auto issue = [&](int st, int64_t t) __attribute__((always_inline)) {
+  // group G (0..3) of this wave's loads of tile t into stage st: loads
+  // G*CHUNK .. (G+1)*CHUNK-1, the A loads first
+  auto issue_group = [&](auto G, int st, int64_t t) __attribute__((always_inline)) {
+    constexpr int g = decltype(G)::value;
     const unsigned char* ga = Ab + t * (DMA_BK * 4);
     const unsigned char* gb = Bb + t * (DMA_BK * 4);
     const uint32_t base = lds0 + uint32_t(st) * DMA_STAGE;
 #pragma unroll
-    for (int i = 0; i < A_LOADS; ++i) dma_load16(voA[i], ga, base + uint32_t(w * A_LOADS + i) * 1024u);
-#pragma unroll
-    for (int i = 0; i < B_LOADS; ++i)
-      dma_load16(voB[i], gb, base + DMA_SA + uint32_t(w * B_LOADS + i) * 1024u);
+    for (int i = g * CHUNK; i < (g + 1) * CHUNK && i < LOADS; ++i) {
+      if (i < A_LOADS) dma_load16(voA[i < A_LOADS ? i : 0], ga, base + uint32_t(w * A_LOADS + i) * 1024u);
+      else
+        dma_load16(voB[i < A_LOADS ? 0 : i - A_LOADS], gb,
+                   base + DMA_SA + uint32_t(w * B_LOADS + i - A_LOADS) * 1024u);
+    }
   };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
 
   int offA[WM], swA[WM], offB[WN], swB[WN];
 #pragma unroll
@@ -934,77 +952,98 @@ __global__ void __launch_bounds__(512, 1) gett_mfma_dma(GettArgs a) {
         for (int bm = 0; bm < WM; ++bm)
           acc[bn][p][bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bf[bn][p], af[cs][bm], acc[bn][p][bm], 0, 0, 0);
   };
-  // the MFMAs of one k step on A set CS and B' operands bf, with the B' of
-  // the next k step (raw set NCS) formed in between: its 16 VALU operations
-  // are spread over the last five MFMAs, so they run while the matrix pipe
-  // is busy instead of in a gap of their own
-  auto mma_next = [&](auto CS, f16x8 (*bf)[2], auto NCS, f16x8 (*bfn)[2]) __attribute__((always_inline)) {
+  // One k step: the fragments of the next k step (raw B first, then A) are
+  // read into register set NCS while the MFMAs of this step run on set CS
+  // and the B' operands bf, and the B' operands of the next step (bfn) are
+  // formed from the raw B read at its start.  The scheduling groups issue
+  // these one by one between MFMAs, so that the matrix pipe is fed while the
+  // reads and the VALU work proceed.
+  auto kstep = [&](auto CS, f16x8 (*bf)[2], f16x8 (*bfn)[2], const unsigned char* rs, int rkk)
+      __attribute__((always_inline)) {
+    constexpr int ncs = decltype(CS)::value ^ 1;
+    using NCS = std::integral_constant<int, ncs>;
+    frags(rs, rkk, ncs);
     mma(CS, bf);
-    bprime(NCS, bfn);
-    __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+    bprime(NCS{}, bfn);
+    constexpr int READS = WM + WN, MFMAS = 2 * WM * WN;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+    for (int i = 0; i < READS; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+    }
+    constexpr int REST = MFMAS - READS, SPREAD = REST >= 8 ? 8 : REST;
+    if constexpr (REST > SPREAD) __builtin_amdgcn_sched_group_barrier(0x008, REST - SPREAD, 0);
+#pragma unroll
+    for (int i = 0; i < SPREAD; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x002, 16 / SPREAD, 0);   // B' VALU
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    // formed in this step (else the compiler sinks it past the next branch)
+#pragma unroll
+    for (int bn = 0; bn < WN; ++bn) asm volatile("" : "+v"(bfn[bn][0]), "+v"(bfn[bn][1]));
   };
   static_assert(DMA_BK == 32, "four k steps per tile");
-  // Pipeline: the fragments of k step j+1 are read (into the other register
-  // set) before the MFMAs of step j are issued, and the scheduling fences
-  // keep the compiler from sinking those reads to their use; the B' operands
-  // of step j+1 are formed during the MFMAs of step j.  Tile t+3 is
-  // requested into the stage of tile t once every wave has passed the
-  // barrier in the last k step of tile t (by then all fragments of tile t
-  // are in registers), so the barrier falls between MFMAs of the same tile
-  // and each load has two tiles of compute to arrive.
+  // Pipeline.  Tile t+3 is requested into the stage of tile t once every wave
+  // has passed the barrier in the last k step of tile t (by then all
+  // fragments of tile t are in registers); its loads are spread over that k
+  // step and the first three of the next tile, a quarter each.  The barrier
+  // falls between MFMAs of the same tile and each load has about two tiles of
+  // compute to arrive.  Branches (the loads of tiles past the end, the wait
+  // count) sit between the k steps, so that each k step is one scheduling
+  // region.
   const int64_t T = K / DMA_BK;
-  issue(0, 0);
-  if (T > 1) issue(1, 1);
-  if (T > 2) issue(2, 2);
-  if (T > 2) wait_loads_barrier<2 * LOADS>();
+  issue_group(I0{}, 0, 0);
+  issue_group(I1{}, 0, 0);
+  issue_group(I2{}, 0, 0);
+  issue_group(I3{}, 0, 0);
+  if (T > 1) {
+    issue_group(I0{}, 1, 1);
+    issue_group(I1{}, 1, 1);
+    issue_group(I2{}, 1, 1);
+    issue_group(I3{}, 1, 1);
+  }
+  if (T > 2) issue_group(I0{}, 2, 2);
+  // tile 0 has landed: only tile 1 and the first group of tile 2 may be in flight
+  if (T > 2) wait_loads_barrier<LOADS + CHUNK>();
   else if (T > 1) wait_loads_barrier<LOADS>();
   else wait_loads_barrier<0>();
   frags(smem, 0, 0);
   f16x8 bfe[WN][2], bfo[WN][2];   // B' operands of even and odd k steps
-  bprime(std::integral_constant<int, 0>{}, bfe);
+  bprime(I0{}, bfe);
   int st = 0;
-  using I0 = std::integral_constant<int, 0>;
-  using I1 = std::integral_constant<int, 1>;
-  // k steps 0..2 of the tile in s
-  auto three_steps = [&](const unsigned char* s) __attribute__((always_inline)) {
-    frags(s, 8, 1);
-    __builtin_amdgcn_sched_barrier(0);
-    mma_next(I0{}, bfe, I1{}, bfo);
-    __builtin_amdgcn_sched_barrier(0);
-    frags(s, 16, 0);
-    __builtin_amdgcn_sched_barrier(0);
-    mma_next(I1{}, bfo, I0{}, bfe);
-    __builtin_amdgcn_sched_barrier(0);
-    frags(s, 24, 1);
-    __builtin_amdgcn_sched_barrier(0);
-    mma_next(I0{}, bfe, I1{}, bfo);
-#pragma unroll
-    for (int bn = 0; bn < WN; ++bn) asm volatile("" : "+v"(bfo[bn][0]), "+v"(bfo[bn][1]));   // formed here
-    __builtin_amdgcn_sched_barrier(0);
-  };
-  // every tile but the last: its k step 3 overlaps the first reads of the next
   for (int64_t t = 0; t + 1 < T; ++t) {
-    const int nst = st == 2 ? 0 : st + 1;
-    three_steps(smem + st * DMA_STAGE);
-    // tile t+1 has landed (only tile t+2's loads may be in flight) and
-    // every wave's reads of tile t have returned: stage st is free
-    if (t + 2 < T) wait_loads_barrier<LOADS>();
-    else wait_loads_barrier<0>();
-    if (t + 3 < T) issue(st, t + 3);
-    frags(smem + nst * DMA_STAGE, 0, 0);
+    const unsigned char* s = smem + st * DMA_STAGE;
+    const int nst = st == 2 ? 0 : st + 1, pst = st == 0 ? 2 : st - 1;   // stages of t+1, t+2
+    const bool more = t + 2 < T;
+    if (more) issue_group(I1{}, pst, t + 2);
     __builtin_amdgcn_sched_barrier(0);
-    mma_next(I1{}, bfo, I0{}, bfe);
+    kstep(I0{}, bfe, bfo, s, 8);
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) issue_group(I2{}, pst, t + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    kstep(I1{}, bfo, bfe, s, 16);
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) issue_group(I3{}, pst, t + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    kstep(I0{}, bfe, bfo, s, 24);
+    __builtin_amdgcn_sched_barrier(0);
+    // tile t+1 has landed (only tile t+2's loads may be in flight) and every
+    // wave's reads of tile t have returned: stage st is free
+    if (more) wait_loads_barrier<LOADS>();
+    else wait_loads_barrier<0>();
+    if (t + 3 < T) issue_group(I0{}, st, t + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    kstep(I1{}, bfo, bfe, smem + nst * DMA_STAGE, 0);
     __builtin_amdgcn_sched_barrier(0);
     st = nst;
   }
-  three_steps(smem + st * DMA_STAGE);
-  mma(I1{}, bfo);
+  {
+    const unsigned char* s = smem + st * DMA_STAGE;
+    kstep(I0{}, bfe, bfo, s, 8);
+    kstep(I1{}, bfo, bfe, s, 16);
+    kstep(I0{}, bfe, bfo, s, 24);
+    mma(I1{}, bfo);
+  }
 
   TO* C = static_cast<TO*>(a.C);
   float lmax = 0.0f;
@@ -1013,7 +1052,7 @@ __global__ void __launch_bounds__(512, 1) gett_mfma_dma(GettArgs a) {
     // staged write-out in the order of the output's strides (as in the
     // large kernels): NT threads, PER elements each
     constexpr int BM = DMA_BM, BN = DMA_BN, SROW = BN + 1, LM = 8, LN = 7, LT = LM + LN;
-    constexpr int LO = 9, PER = (BM * BN) / NT;
+    constexpr int LO = NW == 8 ? 9 : 8, PER = (BM * BN) / NT;
     static_assert((1 << LO) == NT && PER <= NT, "thread bits of the write-out");
     static_assert(BM * SROW * 4 <= 3 * DMA_STAGE, "staged tile fits the operand stages");
     uint32_t* stage = reinterpret_cast<uint32_t*>(smem);
@@ -1239,7 +1278,8 @@ bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
   if (kernel == K_SKINNY) return in_dt == 1 && nn <= 4 && nk >= 2 && nk <= 6 && nm >= (nk == 6 ? 6 : 7);
   // whole 256 x 128 tiles, K a multiple of 32, and per-lane load offsets
   // (row * K * 4 bytes within a 256-row panel) that fit 32 bits
-  if (kernel == K_MFMA_DMA || kernel == K_MFMA_DMA_X) return in_dt == 1 && nm >= 8 && nn >= 7 && nk >= 5 && nk <= 21;
+  if (kernel == K_MFMA_DMA || kernel == K_MFMA_DMA_X || kernel == K_MFMA_DMA4 || kernel == K_MFMA_DMA4_X)
+    return in_dt == 1 && nm >= 8 && nn >= 7 && nk >= 5 && nk <= 21;
   return false;
 }
 
@@ -1268,12 +1308,12 @@ static hipError_t launch_big(const GettArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename TO, int ORDER>
+template <typename TO, int ORDER, int NW>
 static hipError_t launch_dma(const GettArgs& a, hipStream_t s) {
   if (a.nm < 8 || a.nn < 7 || a.nk < 5 || a.nk > 21) return hipErrorInvalidValue;
   const int64_t blocks = (int64_t(1) << a.nz) * ((int64_t(1) << a.nm) / DMA_BM) * ((int64_t(1) << a.nn) / DMA_BN);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gett_mfma_dma<TO, ORDER>), dim3(unsigned(blocks)), dim3(512), 0, s, a);
+  hipLaunchKernelGGL((gett_mfma_dma<TO, ORDER, NW>), dim3(unsigned(blocks)), dim3(64 * NW), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1291,8 +1331,10 @@ static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((gett_mfma<TI, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
   } else {
     if constexpr (std::is_same<TI, _Float16>::value) {
-      if (kernel == K_MFMA_DMA) return launch_dma<TO, 0>(a, s);
-      if (kernel == K_MFMA_DMA_X) return launch_dma<TO, 1>(a, s);
+      if (kernel == K_MFMA_DMA) return launch_dma<TO, 0, 8>(a, s);
+      if (kernel == K_MFMA_DMA_X) return launch_dma<TO, 1, 8>(a, s);
+      if (kernel == K_MFMA_DMA4) return launch_dma<TO, 0, 4>(a, s);
+      if (kernel == K_MFMA_DMA4_X) return launch_dma<TO, 1, 4>(a, s);
       if (kernel == K_MFMA_BIG_X) return launch_big<TO, 4, 2, 2, 1, 32, 1>(a, s);
       if (kernel == K_MFMA_DB_X) return launch_big<TO, 4, 4, 1, 2, 32, 1>(a, s);
       if (kernel == K_MFMA_WIDE_X) return launch_big<TO, 4, 4, 1, 1, 32, 1>(a, s);

@@ -108,7 +108,7 @@ def _applicable(kernel, dt, shape):
         return dt == "chalf" and nm >= 7 and nn >= 6
     if kernel == 7:
         return dt == "chalf" and nn <= 4 and 2 <= nk <= 6 and nm >= (6 if nk == 6 else 7)
-    if kernel in (11, 12):
+    if kernel in (11, 12, 13, 14):
         return dt == "chalf" and nm >= 8 and nn >= 7 and 5 <= nk <= 21
     return True
 
@@ -137,7 +137,7 @@ def _to_half_pairs(x, e):
     return torch.from_numpy(v.astype(np.float16)).cuda()
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_pair_chalf(lf, kernel, shape):
     nz, nm, nn, nk = shape
@@ -187,7 +187,7 @@ def test_pair_mixed_half_a_c64_b(lf, kernel, shape):
 
 
 @pytest.mark.parametrize("kernel,shape", [(1, (0, 7, 5, 6)), (11, (0, 8, 7, 6)), (12, (1, 8, 7, 5)),
-                                          (11, (0, 9, 7, 8)), (12, (1, 8, 8, 5))])
+                                          (13, (0, 9, 7, 8)), (14, (1, 8, 8, 5))])
 def test_pair_half_in_c64_out(lf, kernel, shape):
     nz, nm, nn, nk = shape
     _say(f"pair half in, c64 out kernel={kernel} shape={shape}")
