@@ -697,6 +697,21 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
     uint32_t* stage = reinterpret_cast<uint32_t*>(smem);
     __shared__ int64_t hiAddr[PER];
     __shared__ int hiIdx[PER];
+    __shared__ int64_t sStv[LT];   // the tile's bit strides in ascending order (stable)
+    __shared__ int sBit[LT];       // and which tile bit each is (0..LM-1 m, LM.. n)
+    if (tid < LT) {
+      // rank of bit tid among the LT strides: one thread per bit instead of
+      // a sort in every thread
+      const int64_t v = tid < LM ? a.cm[tid] : a.cn[tid - LM];
+      int r = 0;
+#pragma unroll
+      for (int j = 0; j < LT; ++j) {
+        const int64_t u = j < LM ? a.cm[j] : a.cn[j - LM];
+        r += (u < v) || (u == v && j < tid);
+      }
+      sStv[r] = v;
+      sBit[r] = tid;
+    }
     __syncthreads();   // every wave is done with the operand tiles
 #pragma unroll
     for (int bn = 0; bn < WN; ++bn)
@@ -720,28 +735,17 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
           stage[ml * SROW + nl] = wv;
         }
       }
-    // sort the tile bits by output stride (every thread, same result)
-    int64_t st[LT];
-    int bit[LT];   // tile bit: 0..LM-1 are m bits, LM.. are n bits
-#pragma unroll
-    for (int i = 0; i < LT; ++i) {
-      bit[i] = i;
-      st[i] = i < LM ? a.cm[i] : a.cn[i - LM];
-    }
-    for (int i = 1; i < LT; ++i)
-      for (int j = i; j > 0 && st[j] < st[j - 1]; --j) {
-        const int64_t ts = st[j]; st[j] = st[j - 1]; st[j - 1] = ts;
-        const int tb = bit[j]; bit[j] = bit[j - 1]; bit[j - 1] = tb;
-      }
     // element e = tid + 256 j: its low 8 bits come from tid, the rest from j
     auto split = [&](int e, int lo, int hi, int64_t& addr, int& idx) {
       addr = 0;
       int ml = 0, nl = 0;
+#pragma unroll
       for (int i = lo; i < hi; ++i)
         if ((e >> (i - lo)) & 1) {
-          addr += st[i];
-          if (bit[i] < LM) ml |= 1 << bit[i];
-          else nl |= 1 << (bit[i] - LM);
+          addr += sStv[i];
+          const int b = sBit[i];
+          if (b < LM) ml |= 1 << b;
+          else nl |= 1 << (b - LM);
         }
       idx = ml * SROW + nl;
     };
@@ -753,8 +757,9 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
     if (!a.amax_only) {
       const int64_t base = czv + cmT[0] + cnT[0] + loAddr;
       uint32_t* Cw = reinterpret_cast<uint32_t*>(C);
+      // streaming stores: the tile is written once and read by a later step
 #pragma unroll 8
-      for (int j = 0; j < PER; ++j) Cw[base + hiAddr[j]] = stage[loIdx + hiIdx[j]];
+      for (int j = 0; j < PER; ++j) __builtin_nontemporal_store(stage[loIdx + hiIdx[j]], &Cw[base + hiAddr[j]]);
     }
   } else {
 #pragma unroll
