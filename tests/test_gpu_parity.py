@@ -162,6 +162,49 @@ def test_pair_chalf(lf, kernel, shape):
     assert rel_err(got, ref) < 2e-3
 
 
+# Output layouts of the large complex-half tiles' write-out: n fastest (the
+# two smallest strides are tile bits 1 and 2 apart: 16-byte stores), m
+# fastest, z fastest (strides 1 and 2 outside the tile: 4-byte stores), and
+# n fastest with a z bit between the two lowest n bits.
+def _layout_strides(kind, nz, nm, nn):
+    if kind == "n_fastest":
+        bits = list(range(nz + nm, nz + nm + nn)) + list(range(nz, nz + nm)) + list(range(nz))
+    elif kind == "m_fastest":
+        bits = list(range(nz, nz + nm)) + list(range(nz + nm, nz + nm + nn)) + list(range(nz))
+    elif kind == "z_fastest":
+        bits = list(range(nz)) + list(range(nz + nm, nz + nm + nn)) + list(range(nz, nz + nm))
+    else:  # "split_pair": n0, z0, n1, ...
+        n = list(range(nz + nm, nz + nm + nn))
+        bits = [n[0], 0] + n[1:] + list(range(nz, nz + nm)) + list(range(1, nz))
+    st = np.zeros(nz + nm + nn, np.int64)
+    for p, b in enumerate(bits):
+        st[b] = 1 << p
+    return st
+
+
+@pytest.mark.parametrize("kernel", [2, 5, 8, 11, 12, 13, 14])
+@pytest.mark.parametrize("layout", ["n_fastest", "m_fastest", "z_fastest", "split_pair"])
+def test_pair_chalf_layouts(lf, kernel, layout):
+    nz, nm, nn, nk = 1, 9, 8, 6
+    if not _applicable(kernel, "chalf", (nz, nm, nn, nk)):
+        pytest.skip("kernel variant not applicable to this shape")
+    _say(f"pair chalf layout={layout} kernel={kernel}")
+    A = wl.random_complex((1 << (nz + nm + nk),), seed=41)
+    B = wl.random_complex((1 << (nz + nn + nk),), seed=42)
+    st = _layout_strides(layout, nz, nm, nn)
+    assert sorted(st.tolist()) == [1 << i for i in range(nz + nm + nn)]
+    dA = _to_half_pairs(A, -8)
+    dB = _to_half_pairs(B, -8)
+    dC = torch.zeros((1 << (nz + nm + nn), 2), dtype=torch.float16, device="cuda")
+    lf.contract_pair(dA, dB, dC, nz, nm, nn, nk, st, 2.0 ** -16 * 64, kernel)
+    torch.cuda.synchronize()
+    Ah = (dA.cpu().numpy().astype(np.float64) @ np.array([1, 1j])) * 2.0 ** -8
+    Bh = (dB.cpu().numpy().astype(np.float64) @ np.array([1, 1j])) * 2.0 ** -8
+    ref = _scatter(_ref_pair(Ah, Bh, nz, nm, nn, nk), nz, nm, nn, st) * 64
+    got = dC.cpu().numpy().astype(np.float64) @ np.array([1, 1j])
+    assert rel_err(got, ref) < 2e-3
+
+
 @pytest.mark.parametrize("kernel", [0, 3, 7])
 @pytest.mark.parametrize("shape", [(0, 10, 2, 2), (1, 9, 3, 3), (0, 10, 4, 4), (2, 7, 4, 5),
                                    (0, 6, 3, 6), (0, 8, 0, 6), (0, 13, 2, 2)])
