@@ -695,8 +695,6 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
     constexpr int LM = 8, LN = BN == 128 ? 7 : (BN == 64 ? 6 : 5), LT = LM + LN;
     constexpr int PER = (BM * BN) / 256;   // elements per thread
     uint32_t* stage = reinterpret_cast<uint32_t*>(smem);
-    __shared__ int64_t hiAddr[PER];
-    __shared__ int hiIdx[PER];
     __shared__ int64_t sStv[LT];   // the tile's bit strides in ascending order (stable)
     __shared__ int sBit[LT];       // and which tile bit each is (0..LM-1 m, LM.. n)
     if (tid < LT) {
@@ -752,14 +750,40 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
     int64_t loAddr;
     int loIdx;
     split(tid, 0, 8, loAddr, loIdx);
-    if (tid < PER) split(tid, 8, LT, hiAddr[tid], hiIdx[tid]);
+    // address and staging offsets of the high sorted bits (taken from j),
+    // the same in every thread: scalar registers
+    constexpr int HB = LT - 8;
+    static_assert((1 << HB) == PER, "high bits enumerate the thread's elements");
+    int64_t hS[HB];
+    int hI[HB];
+#pragma unroll
+    for (int b = 0; b < HB; ++b) {
+      const int64_t v = sStv[8 + b];
+      hS[b] = (int64_t(__builtin_amdgcn_readfirstlane(int(v >> 32))) << 32) |
+              uint32_t(__builtin_amdgcn_readfirstlane(int(v)));
+      const int bb = __builtin_amdgcn_readfirstlane(sBit[8 + b]);
+      hI[b] = bb < LM ? (1 << bb) * SROW : (1 << (bb - LM));
+    }
     __syncthreads();
     if (!a.amax_only) {
       const int64_t base = czv + cmT[0] + cnT[0] + loAddr;
       uint32_t* Cw = reinterpret_cast<uint32_t*>(C);
-      // streaming stores: the tile is written once and read by a later step
-#pragma unroll 8
-      for (int j = 0; j < PER; ++j) __builtin_nontemporal_store(stage[loIdx + hiIdx[j]], &Cw[base + hiAddr[j]]);
+      // element j of this thread: offsets built from element j with its
+      // lowest set bit cleared (one scalar add each); streaming stores: the
+      // tile is written once and read by a later step
+      int64_t ad[PER];
+      int ix[PER];
+      ad[0] = 0;
+      ix[0] = 0;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        if (j > 0) {
+          const int b = __builtin_ctz(j);
+          ad[j] = ad[j & (j - 1)] + hS[b];
+          ix[j] = ix[j & (j - 1)] + hI[b];
+        }
+        __builtin_nontemporal_store(stage[loIdx + ix[j]], &Cw[base + ad[j]]);
+      }
     }
   } else {
 #pragma unroll
