@@ -810,7 +810,8 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
 // ------------------------------------------------------------ DMA-fed MFMA
 // The 256 m x 128 n complex tile, run by eight waves (two per SIMD, each
 // 64 m x 64 n, the accumulators in 128 VGPRs) so that one wave's MFMAs cover
-// the other's LDS waits.  The real and imaginary parts of C are separate
+// the other's LDS waits, or by four (one per SIMD, 128 m x 64 n, the
+// accumulators in AGPRs).  The real and imaginary parts of C are separate
 // 32 x 32 MFMA blocks that share the A fragment: each lane reads one whole
 // B row chunk, and both operand forms of it, (Br, -Bi) and (Bi, Br), are
 // made in registers (one operation per 32-bit word), so no two lanes read
