@@ -205,6 +205,31 @@ def test_pair_chalf_layouts(lf, kernel, layout):
     assert rel_err(got, ref) < 2e-3
 
 
+# The streaming kernels over the same layouts.
+@pytest.mark.parametrize("kernel", [0, 3, 7])
+@pytest.mark.parametrize("layout", ["n_fastest", "m_fastest", "z_fastest", "split_pair"])
+@pytest.mark.parametrize("shape", [(1, 9, 4, 2), (2, 8, 2, 4), (1, 10, 3, 3)])
+def test_pair_chalf_streaming_layouts(lf, kernel, layout, shape):
+    nz, nm, nn, nk = shape
+    if not _applicable(kernel, "chalf", shape):
+        pytest.skip("kernel variant not applicable to this shape")
+    _say(f"pair chalf streaming layout={layout} kernel={kernel} shape={shape}")
+    A = wl.random_complex((1 << (nz + nm + nk),), seed=51 + sum(shape))
+    B = wl.random_complex((1 << (nz + nn + nk),), seed=52 + sum(shape))
+    st = _layout_strides(layout, nz, nm, nn)
+    assert sorted(st.tolist()) == [1 << i for i in range(nz + nm + nn)]
+    dA = _to_half_pairs(A, -8)
+    dB = _to_half_pairs(B, -8)
+    dC = torch.zeros((1 << (nz + nm + nn), 2), dtype=torch.float16, device="cuda")
+    lf.contract_pair(dA, dB, dC, nz, nm, nn, nk, st, 2.0 ** -16 * 64, kernel)
+    torch.cuda.synchronize()
+    Ah = (dA.cpu().numpy().astype(np.float64) @ np.array([1, 1j])) * 2.0 ** -8
+    Bh = (dB.cpu().numpy().astype(np.float64) @ np.array([1, 1j])) * 2.0 ** -8
+    ref = _scatter(_ref_pair(Ah, Bh, nz, nm, nn, nk), nz, nm, nn, st) * 64
+    got = dC.cpu().numpy().astype(np.float64) @ np.array([1, 1j])
+    assert rel_err(got, ref) < 2e-3
+
+
 @pytest.mark.parametrize("kernel", [0, 3, 7])
 @pytest.mark.parametrize("shape", [(0, 10, 2, 2), (1, 9, 3, 3), (0, 10, 4, 4), (2, 7, 4, 5),
                                    (0, 6, 3, 6), (0, 8, 0, 6), (0, 13, 2, 2)])
