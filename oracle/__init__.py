@@ -10,5 +10,8 @@ Modules:
   tn    complex128 contraction of one sliced sub-network (numpy)
   topk  top-k selection, XEB (Eq. 1) and its Porter-Thomas expectations
   mlp   float64 reference of the cost-model network (forward, backward)
-  costs independent recount of per-step work from an exported plan
+
+The independent recount of per-step work from an exported plan (multiply-adds
+and the largest tensor, from the oracle's own network) is written out in the
+CPU tests of the boundary, next to the plan it checks.
 """

@@ -283,3 +283,59 @@ def test_golden_prefix_fidelity_is_the_fraction():
         f = abs(np.vdot(ex, pre)) ** 2 / (np.vdot(ex, ex).real * np.vdot(pre, pre).real)
         assert abs(f * 2 ** D - 1) < 0.05, (D, f)
         assert abs(np.vdot(pre, pre).real / np.vdot(ex, ex).real * 2 ** D - 1) < 0.1, D
+
+
+def test_rqc30_stored_statistics():
+    """The stored 30-qubit statistics (written by tests/golden/make_rqc30.py
+    from the oracle's state vector) against what the paper and the
+    Porter-Thomas law fix for them:
+      - unit norm of the state;
+      - moments N*sum q^2 = 2 and N^2*sum q^3 = 6 of Porter-Thomas (Methods
+        B), to +-0.1 and +-0.6 at N = 2^30;
+      - ideal top-2^15 of 2^30 XEB (Methods B, Eq. 2): H_N - H_k = 10.3972
+        to +-0.3, and within one printed standard deviation of the paper's
+        own figure, 10.4694 +- 0.2635;
+      - ideal top-1 per group of 64 correlated strings over 256 groups:
+        H_64 - 1 = 3.744, standard deviation of the mean
+        sqrt(sum_{i=1..64} 1/i^2 / 256) = 0.080 (the maximum of m
+        i.i.d. Exp(1) values is sum_i E_i / i), to 4 sigma."""
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden", "rqc30_stats.json")) as f:
+        st = json.load(f)
+    assert abs(st["norm2"] - 1.0) < 1e-10
+    assert abs(st["N_m2"] - 2.0) < 0.1
+    assert abs(st["N2_m3"] - 6.0) < 0.6
+    ideal = topk.expected_topk_xeb(2 ** 30, 2 ** 15)
+    assert abs(ideal - 10.3972) < 1e-3
+    assert abs(st["xeb_top_2p15_of_2p30"] - ideal) < 0.3
+    assert abs(st["xeb_top_2p15_of_2p30"] - 10.4694) < 0.2635
+    var1 = sum(1.0 / i ** 2 for i in range(1, 65))   # Var of the max of 64 Exp(1)
+    sd = math.sqrt(var1 / 256)
+    assert abs(sd - 0.080) < 0.002
+    assert abs(topk.expected_topk_xeb(64, 1) - 3.744) < 1e-3
+    assert abs(st["xeb_top1_per_group64"] - topk.expected_topk_xeb(64, 1)) < 4 * sd
+
+
+def test_probs_and_moments_on_known_states():
+    """sv.probs and sv.moments (used to write the stored statistics) on states
+    whose values are known in closed form: the uniform superposition of n
+    qubits has q = 2^-n everywhere, so N*sum q^2 = 1 and N^2*sum q^3 = 1;
+    a basis state has N*sum q^2 = N and N^2*sum q^3 = N^2; a hand-made
+    4-entry state checks each entry and the sums term by term."""
+    n = 6
+    N = 1 << n
+    psi = np.full(N, 2.0 ** (-n / 2) * np.exp(0.3j), np.complex128)
+    p = sv.probs(psi)
+    assert np.allclose(p, 2.0 ** -n, rtol=0, atol=1e-18)
+    m2, m3 = sv.moments(psi)
+    assert abs(N * m2 - 1.0) < 1e-12 and abs(N * N * m3 - 1.0) < 1e-12
+    e = np.zeros(N, np.complex128)
+    e[37] = 1j
+    m2, m3 = sv.moments(e)
+    assert abs(N * m2 - N) < 1e-12 and abs(N * N * m3 - N * N) < 1e-9
+    assert sv.probs(e)[37] == 1.0 and sv.probs(e).sum() == 1.0
+    v = np.array([0.6, 0.8j, 0.0, 0.0], np.complex128)   # q = 0.36, 0.64, 0, 0
+    m2, m3 = sv.moments(v)
+    assert np.array_equal(sv.probs(v), topk.probabilities(v))
+    assert abs(m2 - (0.36 ** 2 + 0.64 ** 2)) < 1e-15
+    assert abs(m3 - (0.36 ** 3 + 0.64 ** 3)) < 1e-15
