@@ -57,6 +57,7 @@ enum {
 enum { LF_C64 = 0, LF_CHALF = 1 };          /* contraction arithmetic */
 enum { LF_COST_FLOPMEM = 0, LF_COST_MLP = 1 }; /* path-search cost model */
 enum { LF_LAUNCH_STREAM = 0, LF_LAUNCH_GRAPH = 1 };
+enum { LF_OVERFLOW_RECALIBRATE = 0, LF_OVERFLOW_REPORT = 1 }; /* complex-half saturation policy */
 
 typedef struct lf_gate {
   int32_t n_q;       /* 1 or 2 */
@@ -88,7 +89,7 @@ typedef struct lf_plan_opts {
                                     complex64 */
   int32_t launch_mode;           /* LF_LAUNCH_STREAM or LF_LAUNCH_GRAPH */
   int32_t check_overflow;        /* nonzero: lf_contract_slices synchronizes at its end
-                                    and reports LF_OVERFLOW on saturation */
+                                    and handles saturation by overflow_policy */
   int32_t slices_per_graph;      /* graph mode: slices captured per graph replay */
   int32_t search_dtype;          /* arithmetic whose step costs the search minimises;
                                     -1 = dtype.  Two plans that differ only in dtype and
@@ -102,6 +103,14 @@ typedef struct lf_plan_opts {
                                     of the whole sliced network picks one.  The search
                                     itself (trees, annealing, sliced wires) always runs
                                     on FLOP + memory */
+  int32_t chalf_headroom_bits;   /* complex-half: the shift of each step is calibrated so
+                                    the largest |re|,|im| of its result on the calibration
+                                    slice is at most 2^(16 - this); in [-8, 24], default 4 */
+  int32_t overflow_policy;       /* with check_overflow: LF_OVERFLOW_RECALIBRATE (default)
+                                    re-derives the shifts on the first saturated slice with
+                                    two more bits of headroom and contracts the rest of the
+                                    range again (at most 3 times per call);
+                                    LF_OVERFLOW_REPORT returns LF_OVERFLOW at once */
 } lf_plan_opts;
 
 typedef struct lf_plan_info {
@@ -129,8 +138,8 @@ typedef struct lf_plan lf_plan;
 
 /* Defaults: LF_C64, cap 2^28, planner-chosen slices, FLOP+memory cost,
  * 8 greedy and 64 partition trials, no annealing, seed 1, chalf_min_log2 16,
- * stream launch, autotuning on,
- * overflow check on, 8 slices per graph. */
+ * stream launch, autotuning on, overflow check on with recalibration,
+ * 4 bits of complex-half headroom, 8 slices per graph, 1 restart. */
 void lf_plan_opts_default(lf_plan_opts* opts);
 
 /*
@@ -186,14 +195,59 @@ lf_status lf_plan_bind_workspace(lf_plan* plan, void* dev_ptr, uint64_t bytes, v
  * out_amps (device, complex128, [n_batch][2^l], (re, im) interleaved), in
  * float64, one slice after another in increasing order (deterministic).
  * The full range gives the exact amplitudes; a prefix gives the fraction f
- * of Methods A.  begin == end is a no-op.  Asynchronous on `stream` unless
- * check_overflow is set, in which case it synchronizes and returns
- * LF_OVERFLOW if any complex-half value saturated.  A plan is used by one
- * stream at a time.  Errors: LF_NOT_BOUND, LF_INVALID_ARGUMENT,
- * LF_HIP_ERROR, LF_OVERFLOW.
+ * of Methods A.  begin == end is a no-op.  A plan is used by one stream at a
+ * time.
+ *
+ * Complex-half saturation (an extension; the paper computes in complex64):
+ * a slice in which any value had to be clamped to the half range, and every
+ * slice after it, is NOT added: out_amps always holds the sum of the slices
+ * before the first saturated one, whose number the plan records (see
+ * lf_plan_overflow; the state persists until cleared).  Without
+ * check_overflow the call is asynchronous and the caller reads that state
+ * itself.  With check_overflow the call synchronizes; on saturation the
+ * LF_OVERFLOW_RECALIBRATE policy re-derives the shifts on the first
+ * saturated slice (two more bits of headroom) and contracts the rest of the
+ * range again, so the call returns LF_OK with every slice added; after 3
+ * such attempts, or under LF_OVERFLOW_REPORT, it returns LF_OVERFLOW with
+ * out_amps holding the slices before lf_overflow_info.first_bad_slice.
+ * Errors: LF_NOT_BOUND, LF_INVALID_ARGUMENT, LF_HIP_ERROR, LF_OVERFLOW.
  */
 lf_status lf_contract_slices(lf_plan* plan, int64_t slice_begin, int64_t slice_end,
                              void* out_amps, void* stream);
+
+/* Saturation state of a complex-half plan (complex64 plans read zeros). */
+typedef struct lf_overflow_info {
+  uint32_t saturated;        /* values clamped to the half range since the last clear */
+  int32_t recalibrations;    /* automatic recalibrations since the workspace was bound */
+  int64_t first_bad_slice;   /* first slice left out of an accumulator; -1 = none */
+  int32_t headroom_bits;     /* current calibration headroom (see lf_plan_opts) */
+  int32_t reserved;
+} lf_overflow_info;
+
+/* Reads the saturation state into *out (synchronizes `stream`) and, if
+ * `clear` is nonzero, resets the counter and the recorded slice so later
+ * slices are added again.  Errors: LF_INVALID_ARGUMENT, LF_NOT_BOUND,
+ * LF_HIP_ERROR. */
+lf_status lf_plan_overflow(lf_plan* plan, void* stream, lf_overflow_info* out, int32_t clear);
+
+/* Re-derives the complex-half shift of every step from slice `sigma` with
+ * `headroom_bits` bits of headroom (the largest |re|,|im| of each step's
+ * result on that slice becomes at most 2^(16 - headroom_bits)), recomputes
+ * the slice-independent results with them and clears the saturation state.
+ * A no-op for complex64 plans.  Synchronous.  Errors: LF_INVALID_ARGUMENT,
+ * LF_NOT_BOUND, LF_HIP_ERROR. */
+lf_status lf_plan_recalibrate(lf_plan* plan, int64_t sigma, int32_t headroom_bits, void* stream);
+
+/* Fault injection for tests of the saturation handling (no use in a
+ * computation): multiplies, in the workspace, the entries of the first leaf
+ * that carries sliced wire `wire_bit` whose value of that wire is `value` by
+ * 2^log2_factor, without changing the leaf's recorded exponent, so slices
+ * with bit wire_bit == value carry values 2^log2_factor larger than the
+ * calibration saw.  log2_factor 0 restores the leaf.  Synchronous.  Errors:
+ * LF_INVALID_ARGUMENT (ranges; a complex-half leaf pushed outside the half
+ * range), LF_NOT_BOUND, LF_HIP_ERROR. */
+lf_status lf_debug_scale_slice_leaf(lf_plan* plan, int32_t wire_bit, int32_t value,
+                                    int32_t log2_factor, void* stream);
 
 /*
  * Batched execution of many sliced subtasks of uneven shape.  Item i adds
@@ -207,8 +261,12 @@ lf_status lf_contract_slices(lf_plan* plan, int64_t slice_begin, int64_t slice_e
  * call, timed on temporary accumulators the library allocates and frees,
  * and remember it for this set of plans), and launches it with one
  * hipGraphLaunch on `stream`; the recorded graph is reused while the items
- * are unchanged.  Every plan must be bound.  Results are bit-identical
- * between the modes.  Asynchronous.  Errors: as lf_contract_slices.
+ * are unchanged (and the plans have not been rebound or recalibrated since).
+ * Every plan must be bound.  Results are bit-identical between the modes.
+ * Saturation gating is as in lf_contract_slices (per plan, in item order);
+ * without recalibration: if any item's plan has check_overflow set, the call
+ * synchronizes at its end and returns LF_OVERFLOW when such a plan saturated.
+ * Otherwise asynchronous.  Errors: as lf_contract_slices.
  */
 typedef struct lf_batch_item {
   lf_plan* plan;

@@ -27,6 +27,8 @@ LF_COST_FLOPMEM = 0
 LF_COST_MLP = 1
 LF_LAUNCH_STREAM = 0
 LF_LAUNCH_GRAPH = 1
+LF_OVERFLOW_RECALIBRATE = 0
+LF_OVERFLOW_REPORT = 1
 LF_N_FEATURES = 14
 
 
@@ -49,7 +51,14 @@ class lf_plan_opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("chalf_min_log2", ctypes.c_int32),
                 ("launch_mode", ctypes.c_int32), ("check_overflow", ctypes.c_int32),
                 ("slices_per_graph", ctypes.c_int32), ("search_dtype", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("restarts", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("chalf_headroom_bits", ctypes.c_int32), ("overflow_policy", ctypes.c_int32)]
+
+
+class lf_overflow_info(ctypes.Structure):
+    _fields_ = [("saturated", ctypes.c_uint32), ("recalibrations", ctypes.c_int32),
+                ("first_bad_slice", ctypes.c_int64), ("headroom_bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class lf_batch_item(ctypes.Structure):
@@ -90,6 +99,9 @@ SIGNATURES = {
     "lf_plan_step_strides": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "lf_plan_bind_workspace": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P]),
     "lf_contract_slices": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
+    "lf_plan_overflow": (ctypes.c_int32, [_P, _P, ctypes.POINTER(lf_overflow_info), ctypes.c_int32]),
+    "lf_plan_recalibrate": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int32, _P]),
+    "lf_debug_scale_slice_leaf": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P]),
     "lf_contract_batch": (ctypes.c_int32, [ctypes.POINTER(lf_batch_item), ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_int32, _P]),
     "lf_postselect_topk": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P, _P, _P]),

@@ -18,6 +18,7 @@ DTYPES = {"c64": _lib.LF_C64, "complex64": _lib.LF_C64, "chalf": _lib.LF_CHALF,
           "complex-half": _lib.LF_CHALF}
 COST = {"flopmem": _lib.LF_COST_FLOPMEM, "mlp": _lib.LF_COST_MLP}
 LAUNCH = {"stream": _lib.LF_LAUNCH_STREAM, "graph": _lib.LF_LAUNCH_GRAPH}
+OVERFLOW_POLICY = {"recalibrate": _lib.LF_OVERFLOW_RECALIBRATE, "report": _lib.LF_OVERFLOW_REPORT}
 
 
 def _circuit_struct(circuit):
@@ -54,7 +55,8 @@ class Plan:
                  seed: int = 1, chalf_min_log2: int = 16, launch: str = "stream",
                  check_overflow: bool = True, slices_per_graph: int = 8,
                  search_dtype: Optional[str] = None, autotune: bool = True,
-                 restarts: int = 1):
+                 restarts: int = 1, chalf_headroom_bits: int = 4,
+                 overflow_policy: str = "recalibrate"):
         lib = _lib.load()
         self._lib = lib
         self._handle = ctypes.c_void_p()
@@ -84,6 +86,8 @@ class Plan:
         opts.search_dtype = -1 if search_dtype is None else DTYPES[search_dtype]
         opts.autotune = 1 if autotune else 0
         opts.restarts = int(restarts)
+        opts.chalf_headroom_bits = int(chalf_headroom_bits)
+        opts.overflow_policy = OVERFLOW_POLICY[overflow_policy]
         c, arr = _circuit_struct(circuit)
         openq = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         cb = np.ascontiguousarray(self.closed_bits)
@@ -171,6 +175,23 @@ class Plan:
                                            ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
               "lf_contract_slices")
         return out
+
+    def overflow(self, clear: bool = False, stream=None) -> dict:
+        """lf_plan_overflow: saturation state (synchronizes the stream)."""
+        inf = _lib.lf_overflow_info()
+        check(self._lib.lf_plan_overflow(self._handle, _stream_ptr(stream), ctypes.byref(inf),
+                                         1 if clear else 0), "lf_plan_overflow")
+        return {name: getattr(inf, name) for name, _ in inf._fields_ if name != "reserved"}
+
+    def recalibrate(self, sigma: int, headroom_bits: int = 4, stream=None):
+        check(self._lib.lf_plan_recalibrate(self._handle, int(sigma), int(headroom_bits),
+                                            _stream_ptr(stream)), "lf_plan_recalibrate")
+
+    def debug_scale_slice_leaf(self, wire_bit: int, value: int, log2_factor: int, stream=None):
+        """Fault injection for saturation tests (lf_debug_scale_slice_leaf)."""
+        check(self._lib.lf_debug_scale_slice_leaf(self._handle, int(wire_bit), int(value),
+                                                  int(log2_factor), _stream_ptr(stream)),
+              "lf_debug_scale_slice_leaf")
 
     def profile_steps(self, reps: int = 3, stream=None) -> np.ndarray:
         S = self.info()["n_steps"]

@@ -79,9 +79,13 @@ struct SliceCopy {
 hipError_t launch_instantiate(const SliceCopy* tab, int n_entries, int64_t max_n, char* ws,
                               const int64_t* sigma_dev, int64_t sigma, hipStream_t s);
 
-// out[i] += root[i] * scale for i < n (complex128 accumulator, float64 math)
+// out[i] += root[i] * scale for i < n (complex128 accumulator, float64 math),
+// unless *sat is nonzero (a complex-half value of this slice or an earlier
+// one saturated): then nothing is added and *first_bad = min(*first_bad,
+// slice number), the slice number read from *sigma_dev when it is not null.
 hipError_t launch_accumulate(int root_dt, const void* root, double* out, int64_t n, double scale,
-                             hipStream_t s);
+                             const unsigned* sat, unsigned long long* first_bad,
+                             const int64_t* sigma_dev, int64_t sigma, hipStream_t s);
 
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);

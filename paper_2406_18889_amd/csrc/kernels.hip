@@ -1456,9 +1456,24 @@ hipError_t launch_instantiate(const SliceCopy* tab, int n_entries, int64_t max_n
 }
 
 // ---------------------------------------------------------- accumulate
+// A slice is added only if no complex-half value of the plan saturated since
+// the counter was last cleared: the steps of the slice ran before this
+// kernel on the same stream, so a nonzero counter here means this slice (or
+// an earlier one) was clamped.  The slice is then left out and the smallest
+// such slice number is recorded, so the accumulator holds exactly the slices
+// before the first saturated one.
 template <typename T>
 __global__ void __launch_bounds__(256) accumulate_kernel(const T* root, double* out, int64_t n,
-                                                         double scale) {
+                                                         double scale, const unsigned* sat,
+                                                         unsigned long long* first_bad,
+                                                         const int64_t* sigma_dev, int64_t sigma) {
+  if (sat && *sat) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      const int64_t sg = sigma_dev ? *sigma_dev : sigma;
+      atomicMin(first_bad, (unsigned long long)sg);
+    }
+    return;
+  }
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     float re, im;
@@ -1469,16 +1484,18 @@ __global__ void __launch_bounds__(256) accumulate_kernel(const T* root, double* 
 }
 
 hipError_t launch_accumulate(int root_dt, const void* root, double* out, int64_t n, double scale,
-                             hipStream_t s) {
+                             const unsigned* sat, unsigned long long* first_bad,
+                             const int64_t* sigma_dev, int64_t sigma, hipStream_t s) {
   int64_t b = (n + 255) / 256;
   if (b > 4096) b = 4096;
   if (b < 1) b = 1;
   if (root_dt == 0)
     hipLaunchKernelGGL(accumulate_kernel<float>, dim3(unsigned(b)), dim3(256), 0, s,
-                       static_cast<const float*>(root), out, n, scale);
+                       static_cast<const float*>(root), out, n, scale, sat, first_bad, sigma_dev, sigma);
   else
     hipLaunchKernelGGL(accumulate_kernel<_Float16>, dim3(unsigned(b)), dim3(256), 0, s,
-                       static_cast<const _Float16*>(root), out, n, scale);
+                       static_cast<const _Float16*>(root), out, n, scale, sat, first_bad, sigma_dev,
+                       sigma);
   return hipGetLastError();
 }
 

@@ -15,10 +15,19 @@
 // acc * 2^s where acc is the float32 accumulation of stored operands, and
 // e_C = e_A + e_B - s.  The shift s of each step is calibrated once per plan
 // on the first contracted slice by a pass that only records the largest
-// |re|,|im| of acc, targeting 2^12 (four bits of headroom below the half
-// maximum 65504); later slices reuse it and count every value clamped to the
-// half range.  Results stored as complex64 fold 2^(e_A + e_B) into their
-// scale and carry e = 0.  The final sum into float64 multiplies by 2^e_root.
+// |re|,|im| of acc, targeting 2^(16 - h) (h bits of headroom below the half
+// range, h = 4 by default); later slices reuse it and count every value
+// clamped to the half range.  Results stored as complex64 fold 2^(e_A + e_B)
+// into their scale and carry e = 0.  The final sum into float64 multiplies
+// by 2^e_root.
+//
+// Saturation: the accumulate kernel of a slice adds nothing once the plan's
+// saturation counter is nonzero and records the smallest such slice number,
+// so the caller's accumulator always holds a prefix of the requested range
+// that saw no clamped value.  With check_overflow set, lf_contract_slices
+// then either recalibrates the shifts on the first saturated slice with more
+// headroom and contracts the rest of the range again, or reports
+// LF_OVERFLOW (overflow_policy).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -76,6 +85,8 @@ struct lf_plan {
   std::vector<int64_t> gtab_off;   // per step: byte offset of [offA | offB] tables, -1 if none
   int64_t copy_max_n = 0;
   int64_t off_copies_tab = 0, off_sigma = 0, off_sat = 0, off_amax = 0;
+  // off_sat holds the saturation counter (uint32) and, 8 bytes on, the first
+  // slice left out because of it (uint64, all ones = none)
   uint64_t ws_bytes = 0;
   std::vector<int> variant_steps, invariant_steps;
   // binding
@@ -85,6 +96,9 @@ struct lf_plan {
   bool invariant_done = false;
   bool calibrated = false;
   bool tuned = false;
+  int headroom = 4;                  // calibration target 2^(16 - headroom)
+  int recalibrations = 0;            // automatic recalibrations since bind
+  uint64_t generation = 0;           // bumped whenever recorded launches go stale
   // graph cache
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -110,6 +124,40 @@ namespace {
 using namespace lf;
 
 int leaf_count(const lf_plan* p) { return p->hp.tree.n_leaves; }
+
+unsigned* sat_ptr(const lf_plan* P) { return reinterpret_cast<unsigned*>(P->ws + P->off_sat); }
+unsigned long long* first_bad_ptr(const lf_plan* P) {
+  return reinterpret_cast<unsigned long long*>(P->ws + P->off_sat + 8);
+}
+
+// drops the process-wide batch graph if it records launches of P
+void release_batch_graph_of(lf_plan* P);
+
+// recorded launches (the plan's slice graph, a batch graph) carry shifts,
+// scales and addresses as kernel arguments: drop them when those change
+void drop_plan_graph(lf_plan* P) {
+  if (P->graph_exec) { (void)hipGraphExecDestroy(P->graph_exec); P->graph_exec = nullptr; }
+  if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+  P->generation++;
+  release_batch_graph_of(P);
+}
+
+// Saturation state of the plan: the counter and the first slice left out.
+// Synchronizes the stream.
+lf_status read_sat(lf_plan* P, hipStream_t st, unsigned* sat, uint64_t* first_bad) {
+  unsigned char buf[16];
+  HIPCHK(hipMemcpyAsync(buf, P->ws + P->off_sat, sizeof(buf), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(sat, buf, 4);
+  std::memcpy(first_bad, buf + 8, 8);
+  return LF_OK;
+}
+
+lf_status clear_sat(lf_plan* P, hipStream_t st) {
+  HIPCHK(launch_zero_u32(sat_ptr(P), 1, st));
+  HIPCHK(launch_set_i64(reinterpret_cast<int64_t*>(first_bad_ptr(P)), -1, st));
+  return LF_OK;
+}
 
 // -------------------------------------------------------- memory planning
 std::string plan_memory(lf_plan* P) {
@@ -341,6 +389,7 @@ void propagate_exponents(lf_plan* P) {
 // whose result is stored in half, one pass records max |acc| without
 // storing, then the shift is set and the step runs for real.
 lf_status calibrate(lf_plan* P, int64_t sigma, hipStream_t stream) {
+  drop_plan_graph(P);
   HIPCHK(launch_instantiate(reinterpret_cast<const SliceCopy*>(P->ws + P->off_copies_tab),
                             int(P->copies.size()), P->copy_max_n, P->ws, nullptr, sigma, stream));
   float* amax_dev = reinterpret_cast<float*>(P->ws + P->off_amax);
@@ -357,7 +406,7 @@ lf_status calibrate(lf_plan* P, int64_t sigma, hipStream_t stream) {
       HIPCHK(hipMemcpyAsync(&mx, amax_dev + s, sizeof(float), hipMemcpyDeviceToHost, stream));
       HIPCHK(hipStreamSynchronize(stream));
       int sh = 0;
-      if (mx > 0 && std::isfinite(mx)) sh = 12 - int(std::ceil(std::log2(double(mx))));
+      if (mx > 0 && std::isfinite(mx)) sh = (16 - P->headroom) - int(std::ceil(std::log2(double(mx))));
       P->shift[s] = sh;
       P->exp2[st.out] = P->exp2[st.a] + P->exp2[st.b] - sh;
     } else {
@@ -406,7 +455,8 @@ lf_status run_slice(lf_plan* P, const int64_t* sigma_dev, int64_t sigma, double*
   const int r = P->root;
   const int64_t n = P->net.n_batch << P->net.open_qubits.size();
   HIPCHK(launch_accumulate(P->store_dt[r], P->ws + P->off[r], out, n,
-                           std::ldexp(1.0, P->exp2[r]), stream));
+                           std::ldexp(1.0, P->exp2[r]), sat_ptr(P), first_bad_ptr(P), sigma_dev,
+                           sigma, stream));
   return LF_OK;
 }
 
@@ -435,6 +485,8 @@ void lf_plan_opts_default(lf_plan_opts* o) {
   o->search_dtype = -1;
   o->autotune = 1;
   o->restarts = 1;
+  o->chalf_headroom_bits = 4;
+  o->overflow_policy = LF_OVERFLOW_RECALIBRATE;
 }
 
 const char* lf_last_error(void) { return g_err.c_str(); }
@@ -461,6 +513,10 @@ lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits
       return fail(LF_INVALID_ARGUMENT, "launch_mode");
     if (o.slices_per_graph < 1 || o.slices_per_graph > 1024)
       return fail(LF_INVALID_ARGUMENT, "slices_per_graph must be in [1, 1024]");
+    if (o.chalf_headroom_bits < -8 || o.chalf_headroom_bits > 24)
+      return fail(LF_INVALID_ARGUMENT, "chalf_headroom_bits must be in [-8, 24]");
+    if (o.overflow_policy != LF_OVERFLOW_RECALIBRATE && o.overflow_policy != LF_OVERFLOW_REPORT)
+      return fail(LF_INVALID_ARGUMENT, "overflow_policy");
     std::vector<lf::GateIn> gates(circuit->n_gates);
     for (int g = 0; g < circuit->n_gates; ++g) {
       const lf_gate& G = circuit->gates[g];
@@ -618,8 +674,9 @@ lf_status lf_plan_bind_workspace(lf_plan* P, void* dev_ptr, uint64_t bytes, void
   P->bound = false;
   P->invariant_done = false;
   P->calibrated = P->opts.dtype == LF_C64;
-  if (P->graph_exec) { (void)hipGraphExecDestroy(P->graph_exec); P->graph_exec = nullptr; }
-  if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+  P->headroom = P->opts.chalf_headroom_bits;
+  P->recalibrations = 0;
+  drop_plan_graph(P);
   // leaves: layout, exponent, rounding, upload
   const int L = leaf_count(P);
   std::vector<char> host;
@@ -680,7 +737,8 @@ lf_status lf_plan_bind_workspace(lf_plan* P, void* dev_ptr, uint64_t bytes, void
   if (!P->copies.empty())
     HIPCHK(hipMemcpyAsync(P->ws + P->off_copies_tab, P->copies.data(),
                           P->copies.size() * sizeof(lf::SliceCopy), hipMemcpyHostToDevice, st));
-  HIPCHK(lf::launch_zero_u32(reinterpret_cast<unsigned*>(P->ws + P->off_sat), 1, st));
+  HIPCHK(lf::launch_zero_u32(sat_ptr(P), 1, st));
+  HIPCHK(lf::launch_set_i64(reinterpret_cast<int64_t*>(first_bad_ptr(P)), -1, st));
   HIPCHK(lf::launch_zero_u32(reinterpret_cast<unsigned*>(P->ws + P->off_amax),
                              int64_t(std::max<size_t>(1, P->hp.steps.size())), st));
   // host staging buffer must outlive the copy
@@ -819,30 +877,132 @@ lf_status lf_contract_slices(lf_plan* P, int64_t s0, int64_t s1, void* out_amps,
   double* out = static_cast<double*>(out_amps);
   lf_status r = ensure_ready(P, s0, st);
   if (r) return r;
-  if (P->opts.launch_mode == LF_LAUNCH_GRAPH && (s1 - s0) >= P->opts.slices_per_graph) {
-    r = contract_graph(P, s0, s1 - s0, out, st);
-    if (r) return r;
-  } else {
-    for (int64_t s = s0; s < s1; ++s) {
-      r = run_slice(P, nullptr, s, out, st, P->time_kernel >= 0);
+  int64_t from = s0;
+  for (int attempt = 0;; ++attempt) {
+    if (P->opts.launch_mode == LF_LAUNCH_GRAPH && (s1 - from) >= P->opts.slices_per_graph) {
+      r = contract_graph(P, from, s1 - from, out, st);
       if (r) return r;
+    } else {
+      for (int64_t s = from; s < s1; ++s) {
+        r = run_slice(P, nullptr, s, out, st, P->time_kernel >= 0);
+        if (r) return r;
+      }
     }
-  }
-  if (P->opts.check_overflow) {
+    if (!P->opts.check_overflow) return LF_OK;
     unsigned sat = 0;
-    HIPCHK(hipMemcpyAsync(&sat, P->ws + P->off_sat, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    uint64_t fb = ~uint64_t(0);
+    r = read_sat(P, st, &sat, &fb);
+    if (r) return r;
+    if (!sat) return LF_OK;
+    // out_amps holds [from, fb): every slice from fb on was left out
+    const bool in_range = fb >= uint64_t(from) && fb < uint64_t(s1);
+    if (!in_range || P->opts.overflow_policy == LF_OVERFLOW_REPORT || attempt == 3)
+      return fail(LF_OVERFLOW, "complex-half values saturated: out_amps holds the slices before " +
+                                   std::to_string(int64_t(fb)) + " (lf_plan_overflow)");
+    // re-derive the shifts on the first saturated slice, two bits wider,
+    // and contract the rest of the range again
+    P->headroom = std::min(24, P->headroom + 2);
+    P->recalibrations++;
+    r = clear_sat(P, st);
+    if (!r) r = calibrate(P, int64_t(fb), st);
+    if (!r) r = clear_sat(P, st);
+    if (r) return r;
+    from = int64_t(fb);
+  }
+}
+
+lf_status lf_plan_overflow(lf_plan* P, void* stream, lf_overflow_info* out, int32_t clear) {
+  if (!P || !out) return fail(LF_INVALID_ARGUMENT, "NULL argument");
+  if (!P->bound) return fail(LF_NOT_BOUND, "no workspace bound");
+  hipStream_t st = as_stream(stream);
+  unsigned sat = 0;
+  uint64_t fb = ~uint64_t(0);
+  lf_status r = read_sat(P, st, &sat, &fb);
+  if (r) return r;
+  std::memset(out, 0, sizeof(*out));
+  out->saturated = sat;
+  out->first_bad_slice = fb == ~uint64_t(0) ? -1 : int64_t(fb);
+  out->recalibrations = P->recalibrations;
+  out->headroom_bits = P->headroom;
+  if (clear) {
+    r = clear_sat(P, st);
+    if (r) return r;
     HIPCHK(hipStreamSynchronize(st));
-    if (sat) {
-      HIPCHK(lf::launch_zero_u32(reinterpret_cast<unsigned*>(P->ws + P->off_sat), 1, st));
-      return fail(LF_OVERFLOW, "complex-half values saturated in the contracted range");
+  }
+  return LF_OK;
+}
+
+lf_status lf_plan_recalibrate(lf_plan* P, int64_t sigma, int32_t headroom_bits, void* stream) {
+  if (!P) return fail(LF_INVALID_ARGUMENT, "plan is NULL");
+  if (!P->bound) return fail(LF_NOT_BOUND, "no workspace bound");
+  const int64_t ns = int64_t(1) << P->hp.sliced.size();
+  if (sigma < 0 || sigma >= ns) return fail(LF_INVALID_ARGUMENT, "slice outside [0, n_slices)");
+  if (headroom_bits < -8 || headroom_bits > 24)
+    return fail(LF_INVALID_ARGUMENT, "headroom_bits must be in [-8, 24]");
+  hipStream_t st = as_stream(stream);
+  lf_status r = ensure_ready(P, sigma, st);
+  if (r) return r;
+  if (P->opts.dtype != LF_CHALF) return LF_OK;
+  P->headroom = headroom_bits;
+  r = calibrate(P, sigma, st);
+  if (!r) r = clear_sat(P, st);
+  if (r) return r;
+  HIPCHK(hipStreamSynchronize(st));
+  return LF_OK;
+}
+
+lf_status lf_debug_scale_slice_leaf(lf_plan* P, int32_t wire_bit, int32_t value, int32_t log2_factor,
+                                    void* stream) {
+  if (!P) return fail(LF_INVALID_ARGUMENT, "plan is NULL");
+  if (!P->bound) return fail(LF_NOT_BOUND, "no workspace bound");
+  if (wire_bit < 0 || wire_bit >= int32_t(P->hp.sliced.size()) || (value != 0 && value != 1) ||
+      log2_factor < -60 || log2_factor > 60)
+    return fail(LF_INVALID_ARGUMENT, "wire_bit, value or log2_factor out of range");
+  // the first leaf whose per-slice copy depends on sliced wire `wire_bit`
+  int leaf = -1;
+  int64_t stride_elems = 0;
+  for (const SliceCopy& c : P->copies) {
+    for (int i = 0; i < c.nbits && leaf < 0; ++i)
+      if (c.t[i] == wire_bit) {
+        for (int l = 0; l < leaf_count(P); ++l)
+          if (P->full_off[l] == c.src) leaf = l;
+        stride_elems = c.stride[i] / c.es;
+      }
+    if (leaf >= 0) break;
+  }
+  if (leaf < 0) return fail(LF_INTERNAL, "no leaf carries that sliced wire");
+  std::vector<cd> lay;
+  leaf_layout(P, leaf, lay);
+  const double f = std::ldexp(1.0, log2_factor);
+  for (size_t e = 0; e < lay.size(); ++e)
+    if (int64_t((int64_t(e) / stride_elems) & 1) == value) lay[e] *= f;
+  std::vector<char> host;
+  if (P->store_dt[leaf] == 0) {
+    host.resize(lay.size() * 8);
+    float* h = reinterpret_cast<float*>(host.data());
+    for (size_t e = 0; e < lay.size(); ++e) { h[2 * e] = float(lay[e].real()); h[2 * e + 1] = float(lay[e].imag()); }
+  } else {
+    host.resize(lay.size() * 4);
+    _Float16* h = reinterpret_cast<_Float16*>(host.data());
+    for (size_t e = 0; e < lay.size(); ++e) {
+      const double re = std::ldexp(lay[e].real(), -P->exp2[leaf]);
+      const double im = std::ldexp(lay[e].imag(), -P->exp2[leaf]);
+      if (std::fabs(re) > 65504.0 || std::fabs(im) > 65504.0)
+        return fail(LF_INVALID_ARGUMENT, "factor takes a complex-half leaf outside the half range");
+      h[2 * e] = (_Float16)float(re);
+      h[2 * e + 1] = (_Float16)float(im);
     }
   }
+  hipStream_t st = as_stream(stream);
+  HIPCHK(hipMemcpyAsync(P->ws + P->full_off[leaf], host.data(), host.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
   return LF_OK;
 }
 
 namespace {
 struct BatchGraph {
-  std::vector<std::tuple<lf_plan*, int64_t, int64_t, void*>> key;
+  // (plan, its generation when recorded, slice range, accumulator) per item
+  std::vector<std::tuple<lf_plan*, uint64_t, int64_t, int64_t, void*>> key;
   int lanes = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -855,9 +1015,19 @@ struct BatchGraph {
     graph = nullptr;
   }
 };
-std::mutex g_batch_mu;
+std::recursive_mutex g_batch_mu;
 BatchGraph g_batch;
 std::map<std::vector<lf_plan*>, int> g_lane_choice;  // tuned lanes per set of plans
+
+bool batch_uses(const BatchGraph& bg, const lf_plan* P) {
+  for (auto& k : bg.key)
+    if (std::get<0>(k) == P) return true;
+  return false;
+}
+
+auto batch_key_of(const lf_batch_item& it) {
+  return std::make_tuple(it.plan, it.plan->generation, it.slice_begin, it.slice_end, it.out_amps);
+}
 
 lf_status record_batch(const lf_batch_item* items, int n, int lanes, BatchGraph& bg) {
   bg.release();
@@ -906,8 +1076,44 @@ lf_status record_batch(const lf_batch_item* items, int n, int lanes, BatchGraph&
   HIPCHK(hipGraphInstantiate(&bg.exec, g, nullptr, nullptr, 0));
   bg.lanes = lanes;
   bg.key.clear();
-  for (int i = 0; i < n; ++i)
-    bg.key.emplace_back(items[i].plan, items[i].slice_begin, items[i].slice_end, items[i].out_amps);
+  for (int i = 0; i < n; ++i) bg.key.push_back(batch_key_of(items[i]));
+  return LF_OK;
+}
+
+void release_batch_graph_of(lf_plan* P) {
+  std::lock_guard<std::recursive_mutex> lk(g_batch_mu);
+  if (batch_uses(g_batch, P)) {
+    g_batch.release();
+    g_batch.key.clear();
+  }
+}
+
+void forget_plan(lf_plan* P) {
+  std::lock_guard<std::recursive_mutex> lk(g_batch_mu);
+  release_batch_graph_of(P);
+  for (auto it = g_lane_choice.begin(); it != g_lane_choice.end();) {
+    if (std::find(it->first.begin(), it->first.end(), P) != it->first.end()) it = g_lane_choice.erase(it);
+    else ++it;
+  }
+}
+
+// After a batch: for every plan with check_overflow set, LF_OVERFLOW if its
+// saturation counter is nonzero (synchronizes the stream).
+lf_status batch_overflow(const lf_batch_item* items, int n, hipStream_t st) {
+  std::vector<lf_plan*> seen;
+  for (int i = 0; i < n; ++i) {
+    lf_plan* P = items[i].plan;
+    if (!P->opts.check_overflow || std::find(seen.begin(), seen.end(), P) != seen.end()) continue;
+    seen.push_back(P);
+    unsigned sat = 0;
+    uint64_t fb = ~uint64_t(0);
+    lf_status r = read_sat(P, st, &sat, &fb);
+    if (r) return r;
+    if (sat)
+      return fail(LF_OVERFLOW, "complex-half values saturated in the batch (item " + std::to_string(i) +
+                                   "): its plan's accumulator holds the slices before " +
+                                   std::to_string(int64_t(fb)) + " in item order (lf_plan_overflow)");
+  }
   return LF_OK;
 }
 }  // namespace
@@ -936,9 +1142,9 @@ lf_status lf_contract_batch(const lf_batch_item* items, int32_t n, int32_t mode,
         lf_status r = run_slice(items[i].plan, nullptr, sg, static_cast<double*>(items[i].out_amps), st);
         if (r) return r;
       }
-    return LF_OK;
+    return batch_overflow(items, n, st);
   }
-  std::lock_guard<std::mutex> lk(g_batch_mu);
+  std::lock_guard<std::recursive_mutex> lk(g_batch_mu);
   std::vector<lf_plan*> pset;
   for (int i = 0; i < n; ++i) pset.push_back(items[i].plan);
   std::sort(pset.begin(), pset.end());
@@ -993,15 +1199,13 @@ lf_status lf_contract_batch(const lf_batch_item* items, int32_t n, int32_t mode,
     }
   }
   bool same = g_batch.exec && g_batch.lanes == lanes && int(g_batch.key.size()) == n;
-  for (int i = 0; same && i < n; ++i)
-    same = g_batch.key[i] == std::make_tuple(items[i].plan, items[i].slice_begin, items[i].slice_end,
-                                             items[i].out_amps);
+  for (int i = 0; same && i < n; ++i) same = g_batch.key[i] == batch_key_of(items[i]);
   if (!same) {
     lf_status r = record_batch(items, n, lanes, g_batch);
     if (r) return r;
   }
   HIPCHK(hipGraphLaunch(g_batch.exec, st));
-  return LF_OK;
+  return batch_overflow(items, n, st);
 }
 
 lf_status lf_postselect_topk(const void* amps, int64_t n_groups, int64_t group_size, int32_t k,
@@ -1135,6 +1339,10 @@ lf_status lf_contract_pair(int32_t dtype_a, int32_t dtype_b, int32_t dtype_out, 
   return LF_OK;
 }
 
-void lf_plan_destroy(lf_plan* P) { delete P; }
+void lf_plan_destroy(lf_plan* P) {
+  if (!P) return;
+  forget_plan(P);
+  delete P;
+}
 
 }  // extern "C"
