@@ -284,11 +284,31 @@ lf_status lf_contract_batch(const lf_batch_item* items, int32_t n_items, int32_t
  * position ascending; writes the first k positions to out_idx[g*k + r]
  * (int64, device) and their p to out_prob (float64, device).  group_size =
  * 2^l gives one selection per closed string; group_size = n_batch * 2^l
- * selects over all candidates.  Limits: 1 <= k <= min(group_size, 1024),
- * group_size <= 2^26.  Errors: LF_INVALID_ARGUMENT, LF_HIP_ERROR.
+ * selects over all candidates (the paper's global top-k over S~).  Limits:
+ * 1 <= k <= group_size, n_groups * group_size <= 2^40, n_groups * k <= 2^31;
+ * amps 16-byte aligned.  Small selections (group_size <= 2^16 and k <= 1024)
+ * run one workgroup per group and are asynchronous.  Larger ones select
+ * with device-side radix selection over the bit patterns of p (p >= 0 orders
+ * as its bits do), an ordered compaction and a stable radix sort, group after
+ * group; they use device scratch of about 16 k bytes + 100 KiB that this
+ * call allocates and frees, so they synchronize `stream`.  The result is the
+ * same either way.  p of a NaN amplitude is unordered: its position in the
+ * result is unspecified.  Errors: LF_INVALID_ARGUMENT, LF_HIP_ERROR.
  */
 lf_status lf_postselect_topk(const void* amps, int64_t n_groups, int64_t group_size, int32_t k,
                              int64_t* out_idx, double* out_prob, void* stream);
+
+/*
+ * p of selected amplitudes, for the cross-entropy benchmark of a selection
+ * (Methods B, Eq. 1: XEB = N/|S| sum over S of q - 1, with q the ideal
+ * probabilities): out_prob[r] = re*re + im*im (float64, no fused rounding) of
+ * element idx[r] of the n complex128 amplitudes at amps (device), NaN where
+ * idx[r] is outside [0, n).  All pointers device memory; asynchronous.
+ * Errors: LF_INVALID_ARGUMENT, LF_HIP_ERROR.
+ */
+lf_status lf_probabilities_at(const void* amps, int64_t n, const int64_t* idx, int64_t m,
+                              double* out_prob, void* stream);
+
 
 /*
  * Times every step of slice 0 on `stream` with HIP events (reps runs each,

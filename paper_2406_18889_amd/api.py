@@ -272,6 +272,23 @@ def postselect_topk(amps, group_size: int, k: int, stream=None):
     return idx, prob
 
 
+def probabilities_at(amps, idx, stream=None):
+    """p (float64, each product and the sum rounded separately) of the
+    amplitudes at positions idx (int64 device tensor) of the flat complex128
+    device tensor amps; NaN for a position outside it."""
+    import torch
+    if amps.dtype != torch.complex128 or not amps.is_contiguous() or not amps.is_cuda:
+        raise ValueError("amps must be a contiguous complex128 CUDA tensor")
+    if idx.dtype != torch.int64 or not idx.is_contiguous() or not idx.is_cuda:
+        raise ValueError("idx must be a contiguous int64 CUDA tensor")
+    out = torch.empty(idx.numel(), dtype=torch.float64, device=amps.device)
+    check(_lib.load().lf_probabilities_at(ctypes.c_void_p(amps.data_ptr()), amps.numel(),
+                                          ctypes.c_void_p(idx.data_ptr()), idx.numel(),
+                                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+          "lf_probabilities_at")
+    return out
+
+
 def contract_pair(A, B, C, nz: int, nm: int, nn: int, nk: int, c_strides, scale: float = 1.0,
                   kernel: int = -1, stream=None):
     """lf_contract_pair on device tensors.  A, B, C are torch tensors holding

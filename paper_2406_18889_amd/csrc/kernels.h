@@ -91,6 +91,22 @@ hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t s);
 
+// p = re*re + im*im with each product and the sum rounded separately (the
+// compiler must not fuse them into a multiply-add)
+__device__ __forceinline__ double prob_of(double re, double im) {
+#pragma clang fp contract(off)
+  const double rr = re * re;
+  const double ii = im * im;
+  return rr + ii;
+}
+
+// select.hip: selection at any size (radix select, ordered compaction,
+// stable sort); scratch of select_scratch_bytes(k) bytes, 256-byte aligned
+uint64_t select_scratch_bytes(int64_t k);
+bool select_uses_radix(int64_t group_size, int k);
+hipError_t launch_select(const double* amps, int64_t n_groups, int64_t group_size, int64_t k,
+                         int64_t* out_idx, double* out_prob, void* scratch, hipStream_t s);
+
 hipError_t launch_topk(const double* amps, int64_t n_groups, int64_t group_size, int k,
                        int64_t* out_idx, double* out_prob, hipStream_t s);
 

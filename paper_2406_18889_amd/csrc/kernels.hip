@@ -1530,15 +1530,6 @@ __device__ __forceinline__ bool topk_better(double p, int64_t j, double q, int64
   return p > q || (p == q && j < i);
 }
 
-// p = re*re + im*im with each product and the sum rounded separately (the
-// compiler must not fuse them into a multiply-add)
-__device__ __forceinline__ double prob_of(double re, double im) {
-#pragma clang fp contract(off)
-  const double rr = re * re;
-  const double ii = im * im;
-  return rr + ii;
-}
-
 __global__ void __launch_bounds__(256) topk_kernel(const double* amps, int64_t group_size, int k,
                                                    int64_t* out_idx, double* out_prob) {
   __shared__ double sp[4];

@@ -68,6 +68,11 @@ constexpr int64_t ALIGN = 256;
 int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 }  // namespace
 
+namespace lf {
+// error reporting for the entry points of the other sources
+lf_status set_error(lf_status s, const std::string& msg) { return fail(s, msg); }
+}  // namespace lf
+
 struct lf_plan {
   lf_plan_opts opts{};
   lf::Network net;
@@ -1206,18 +1211,6 @@ lf_status lf_contract_batch(const lf_batch_item* items, int32_t n, int32_t mode,
   }
   HIPCHK(hipGraphLaunch(g_batch.exec, st));
   return batch_overflow(items, n, st);
-}
-
-lf_status lf_postselect_topk(const void* amps, int64_t n_groups, int64_t group_size, int32_t k,
-                             int64_t* out_idx, double* out_prob, void* stream) {
-  if (n_groups < 0) return fail(LF_INVALID_ARGUMENT, "n_groups < 0");
-  if (n_groups == 0) return LF_OK;
-  if (!amps || !out_idx || !out_prob) return fail(LF_INVALID_ARGUMENT, "NULL pointer");
-  if (group_size < 1 || group_size > (int64_t(1) << 26)) return fail(LF_INVALID_ARGUMENT, "group_size out of range");
-  if (k < 1 || k > 1024 || k > group_size) return fail(LF_INVALID_ARGUMENT, "k out of range");
-  HIPCHK(lf::launch_topk(static_cast<const double*>(amps), n_groups, group_size, k, out_idx, out_prob,
-                         as_stream(stream)));
-  return LF_OK;
 }
 
 lf_status lf_profile_steps(lf_plan* P, int32_t reps, double* out_ms, void* stream) {
