@@ -299,6 +299,22 @@ lf_status lf_postselect_topk(const void* amps, int64_t n_groups, int64_t group_s
                              int64_t* out_idx, double* out_prob, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * selection, arguments and result as lf_postselect_topk, but the large-size
+ * path keeps its scratch in a fixed 64 MiB device array that the library
+ * holds on each GPU it runs on until the process ends, so the call allocates
+ * nothing and is asynchronous on `stream` in every case.  Limit: k <= about
+ * 4.17 million (scratch of about 16.06 k bytes + 97 KiB); a larger k returns
+ * LF_INVALID_ARGUMENT.  Every call on one GPU shares that GPU's array:
+ * calls that may overlap in time on one GPU (different streams, threads)
+ * race and must be serialized by the caller.  Errors: LF_INVALID_ARGUMENT,
+ * LF_HIP_ERROR.
+ */
+lf_status lf_postselect_topk_noalloc(const void* amps, int64_t n_groups, int64_t group_size,
+                                     int32_t k, int64_t* out_idx, double* out_prob, void* stream);
+
+/*
  * p of selected amplitudes, for the cross-entropy benchmark of a selection
  * (Methods B, Eq. 1: XEB = N/|S| sum over S of q - 1, with q the ideal
  * probabilities): out_prob[r] = re*re + im*im (float64, no fused rounding) of

@@ -272,6 +272,28 @@ def postselect_topk(amps, group_size: int, k: int, stream=None):
     return idx, prob
 
 
+def postselect_topk_noalloc(amps, group_size: int, k: int, out_idx, out_prob, stream=None):
+    """lf_postselect_topk_noalloc: the same selection into caller-provided
+    int64 / float64 device tensors of [n_groups, k], with no device
+    allocation (fixed library scratch; overlapping calls on one GPU race)."""
+    import torch
+    if amps.dtype != torch.complex128 or not amps.is_contiguous() or not amps.is_cuda:
+        raise ValueError("amps must be a contiguous complex128 CUDA tensor")
+    n = amps.numel()
+    if group_size <= 0 or n % group_size:
+        raise ValueError("amplitude count must be a multiple of group_size")
+    g = n // group_size
+    for t, dt in ((out_idx, torch.int64), (out_prob, torch.float64)):
+        if t.dtype != dt or not t.is_contiguous() or not t.is_cuda or t.numel() != g * k:
+            raise ValueError("outputs must be contiguous CUDA tensors of n_groups * k elements")
+    check(_lib.load().lf_postselect_topk_noalloc(ctypes.c_void_p(amps.data_ptr()), g, group_size, k,
+                                                 ctypes.c_void_p(out_idx.data_ptr()),
+                                                 ctypes.c_void_p(out_prob.data_ptr()),
+                                                 _stream_ptr(stream)),
+          "lf_postselect_topk_noalloc")
+    return out_idx, out_prob
+
+
 def probabilities_at(amps, idx, stream=None):
     """p (float64, each product and the sum rounded separately) of the
     amplitudes at positions idx (int64 device tensor) of the flat complex128

@@ -30,7 +30,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/leapfrog.h"
 #include "kernels.h"
@@ -408,6 +410,36 @@ hipError_t launch_select(const double* amps, int64_t n_groups, int64_t group_siz
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- fixed scratch
+constexpr uint64_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+int64_t noalloc_max_k() {
+  int64_t k = int64_t(NOALLOC_SCRATCH_BYTES / 17);
+  while (k > 1 && select_scratch_bytes(k) > NOALLOC_SCRATCH_BYTES) --k;
+  return k;
+}
+
+// device address of `scratch` on the current device, looked up once per device
+lf_status noalloc_scratch(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> ptr;  // indexed by device
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(LF_HIP_ERROR, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev >= int(ptr.size())) ptr.resize(dev + 1, nullptr);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(LF_HIP_ERROR, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return LF_OK;
+}
+
 }  // namespace lf
 
 using lf::set_error;
@@ -442,6 +474,45 @@ lf_status lf_postselect_topk(const void* amps, int64_t n_groups, int64_t group_s
   hipError_t e2 = hipStreamSynchronize(st);
   (void)hipFree(scratch);
   if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) return set_error(LF_HIP_ERROR, std::string("top-k selection: ") + hipGetErrorString(e));
+  return LF_OK;
+}
+
+// Entry point for callers that cannot allocate (stream capture, serving
+// loops): the radix path's scratch is a file-scope device array of fixed
+// size, one copy per GPU, addressed through the pointer that
+// hipGetSymbolAddress returns on that device (the array's name in host code
+// is not a device address).
+lf_status lf_postselect_topk_noalloc(const void* amps, int64_t n_groups, int64_t group_size, int32_t k,
+                                     int64_t* out_idx, double* out_prob, void* stream) {
+  if (n_groups < 0) return set_error(LF_INVALID_ARGUMENT, "n_groups < 0");
+  if (n_groups == 0) return LF_OK;
+  if (!amps || !out_idx || !out_prob) return set_error(LF_INVALID_ARGUMENT, "NULL pointer");
+  if (reinterpret_cast<uintptr_t>(amps) % 16 != 0)
+    return set_error(LF_INVALID_ARGUMENT, "amps must be 16-byte aligned");
+  if (group_size < 1 || group_size > (int64_t(1) << 40))
+    return set_error(LF_INVALID_ARGUMENT, "group_size out of range");
+  if (n_groups > (int64_t(1) << 40) / group_size)
+    return set_error(LF_INVALID_ARGUMENT, "n_groups * group_size above 2^40");
+  if (k < 1 || k > group_size) return set_error(LF_INVALID_ARGUMENT, "k out of range");
+  if (int64_t(k) * n_groups > (int64_t(1) << 31))
+    return set_error(LF_INVALID_ARGUMENT, "n_groups * k above 2^31");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double* a = static_cast<const double*>(amps);
+  if (!lf::select_uses_radix(group_size, k)) {
+    hipError_t e = lf::launch_topk(a, n_groups, group_size, k, out_idx, out_prob, st);
+    if (e != hipSuccess) return set_error(LF_HIP_ERROR, std::string("top-k launch: ") + hipGetErrorString(e));
+    return LF_OK;
+  }
+  if (lf::select_scratch_bytes(k) > lf::NOALLOC_SCRATCH_BYTES)
+    return set_error(LF_INVALID_ARGUMENT, "k needs more than the fixed " +
+                                              std::to_string(lf::NOALLOC_SCRATCH_BYTES >> 20) +
+                                              " MiB of scratch of lf_postselect_topk_noalloc (k <= " +
+                                              std::to_string(lf::noalloc_max_k()) + ")");
+  void* scratch = nullptr;
+  lf_status r = lf::noalloc_scratch(&scratch);
+  if (r != LF_OK) return r;
+  hipError_t e = lf::launch_select(a, n_groups, group_size, k, out_idx, out_prob, scratch, st);
   if (e != hipSuccess) return set_error(LF_HIP_ERROR, std::string("top-k selection: ") + hipGetErrorString(e));
   return LF_OK;
 }
