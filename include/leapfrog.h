@@ -325,6 +325,24 @@ lf_status lf_postselect_topk_noalloc(const void* amps, int64_t n_groups, int64_t
 lf_status lf_probabilities_at(const void* amps, int64_t n, const int64_t* idx, int64_t m,
                               double* out_prob, void* stream);
 
+/*
+ * Sampling baseline of Methods B (Eq. 3: samples drawn from the approximate
+ * p of a fraction-f contraction have XEB close to f): n_chains independent
+ * Metropolis chains over the candidate set S~ = {group_base[g] + j * stride :
+ * g < n_groups, j < group_size} of positions in the n_amps complex128
+ * amplitudes at amps (device).  Each chain proposes a uniform candidate and
+ * moves with probability min(1, p_new / p_cur), p = re*re + im*im (float64,
+ * no fused rounding; 0 outside [0, n_amps)); after burn_in moves it writes
+ * every thin-th position to out_pos[chain * per_chain + i] (int64 device,
+ * n_chains * per_chain) and its accepted moves to out_accepted[chain].
+ * Random numbers: one SplitMix64 sequence per chain from `seed`.  group_base
+ * is an int64 device array.  Asynchronous.  Errors: LF_INVALID_ARGUMENT,
+ * LF_HIP_ERROR.
+ */
+lf_status lf_mcmc_sample(const void* amps, int64_t n_amps, const int64_t* group_base, int64_t n_groups,
+                         int64_t group_size, int64_t stride, int64_t n_chains, int64_t burn_in,
+                         int64_t thin, int64_t per_chain, uint64_t seed, int64_t* out_pos,
+                         int64_t* out_accepted, void* stream);
 
 /*
  * Times every step of slice 0 on `stream` with HIP events (reps runs each,

@@ -5,5 +5,5 @@ post-selection (arXiv 2406.18889) on MI355X: a C-ABI HIP library
 
 from .api import (Plan, autotune_load, autotune_save, build_network,  # noqa: F401
                   contract_batch, contract_pair, contract_slices, postselect_topk,
-                  probabilities_at)
+                  probabilities_at, mcmc_sample)
 from ._lib import LeapfrogError  # noqa: F401

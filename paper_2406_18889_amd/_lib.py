@@ -106,6 +106,9 @@ SIGNATURES = {
                                            ctypes.c_int32, _P]),
     "lf_postselect_topk": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P, _P, _P]),
     "lf_probabilities_at": (ctypes.c_int32, [_P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P]),
+    "lf_mcmc_sample": (ctypes.c_int32, [_P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_uint64, _P, _P, _P]),
     "lf_postselect_topk_noalloc": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                                     _P, _P, _P]),
     "lf_profile_steps": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _P]),

@@ -311,6 +311,27 @@ def probabilities_at(amps, idx, stream=None):
     return out
 
 
+def mcmc_sample(amps, group_base, group_size: int, stride: int, n_chains: int, burn_in: int,
+                thin: int, per_chain: int, seed: int, stream=None):
+    """lf_mcmc_sample: Metropolis samples from p over the candidate set
+    {group_base[g] + j * stride : j < group_size} of the flat complex128
+    device tensor amps.  Returns (positions int64 [n_chains * per_chain],
+    accepted moves int64 [n_chains])."""
+    import torch
+    if amps.dtype != torch.complex128 or not amps.is_contiguous() or not amps.is_cuda:
+        raise ValueError("amps must be a contiguous complex128 CUDA tensor")
+    if group_base.dtype != torch.int64 or not group_base.is_contiguous() or not group_base.is_cuda:
+        raise ValueError("group_base must be a contiguous int64 CUDA tensor")
+    out = torch.empty(n_chains * per_chain, dtype=torch.int64, device=amps.device)
+    acc = torch.empty(n_chains, dtype=torch.int64, device=amps.device)
+    check(_lib.load().lf_mcmc_sample(ctypes.c_void_p(amps.data_ptr()), amps.numel(),
+                                     ctypes.c_void_p(group_base.data_ptr()), group_base.numel(),
+                                     group_size, stride, n_chains, burn_in, thin, per_chain, seed,
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(acc.data_ptr()),
+                                     _stream_ptr(stream)), "lf_mcmc_sample")
+    return out, acc
+
+
 def contract_pair(A, B, C, nz: int, nm: int, nn: int, nk: int, c_strides, scale: float = 1.0,
                   kernel: int = -1, stream=None):
     """lf_contract_pair on device tensors.  A, B, C are torch tensors holding

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libleapfrog.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["network.cpp", "planner.cpp", "costmodel.hip", "kernels.hip", "runtime.hip",
-           "mlp.hip", "select.hip"]
+           "mlp.hip", "select.hip", "sample.hip"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
