@@ -145,7 +145,7 @@ void lf_plan_opts_default(lf_plan_opts* opts);
 /*
  * Builds the network of `circuit` with output qubits `open_qubits` (l of
  * them, l <= 30) and `n_batch` closed strings `closed_bits` (each a full
- * n-bit mask; bits at open positions are ignored; n_batch <= 2^20, padded
+ * n-bit mask; bits at open positions are ignored; n_batch <= 2^22, padded
  * internally to a power of two), folds single-qubit gates in float64,
  * searches a contraction tree and slicing under the cap (Methods C, D), lays
  * out every tensor (dimension order, Methods C) and returns an opaque plan

@@ -8,7 +8,7 @@
 
 namespace lf {
 
-constexpr int MAXZ = 20;
+constexpr int MAXZ = 24;
 constexpr int MAXMN = 40;
 
 // One pairwise contraction C[z,m,n] = sum_k A[z,m,k] * B[z,n,k] over complex

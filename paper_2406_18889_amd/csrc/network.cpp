@@ -110,7 +110,7 @@ std::string build_network(int n, const std::vector<GateIn>& gates,
   if (closed_bits.empty()) return "need at least one closed string";
   net.n_batch = int64_t(closed_bits.size());
   if (n_closed == 0 && net.n_batch != 1) return "no closed qubits: batch must be 1";
-  if (net.n_batch > (int64_t(1) << 20)) return "batch too large (max 2^20)";
+  if (net.n_batch > (int64_t(1) << 22)) return "batch too large (max 2^22)";
   int nb = 0;
   while ((int64_t(1) << nb) < net.n_batch) ++nb;
   if (n_closed == 0) nb = 0;
