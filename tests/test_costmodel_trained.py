@@ -91,3 +91,40 @@ def test_trained_network_gpu_forward_matches_oracle_on_heldout():
     got = costmodel.predict(model, h["X"][:2000])
     ref = _oracle_predict(m, h["X"][:2000])
     assert np.max(np.abs(got - ref)) < 1e-3 * max(1.0, float(np.max(np.abs(ref))))
+
+
+AB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                  "costmodel_ab_rqc53.json")
+
+
+@pytest.mark.skipif(not os.path.exists(AB), reason="end-to-end comparison record not committed")
+def test_end_to_end_record_of_the_learned_ranking():
+    """The committed end-to-end comparison (measured runtime as the judge):
+    seeded 53-qubit, 20-cycle circuits planned twice with the same seeds and
+    restarts, the refined candidate kept by the FLOP+memory cost or by the
+    trained network, each plan's slices/s measured on the GPU and its
+    whole-network time = 2^S / (slices/s).  The record must cover at least
+    six circuits, and its reported gains must follow from its own measured
+    fields (the geometric mean of FLOP+memory network time over learned
+    network time).  The value itself is the result, whichever side of 1 it
+    falls on."""
+    import json
+    import math
+    with open(AB) as f:
+        rec = json.load(f)
+    runs = rec["runs"]
+    assert rec["circuits"] == len(runs) >= 6
+    logs = []
+    for r in runs:
+        for side in ("flopmem", "mlp"):
+            assert r[side]["slices_per_s"] > 0
+            t = r[side]["n_sliced"] - math.log2(r[side]["slices_per_s"])
+            assert abs(t - r[side]["log2_network_seconds"]) < 1e-9
+        g = 2.0 ** (r["flopmem"]["log2_network_seconds"] - r["mlp"]["log2_network_seconds"])
+        assert abs(g / r["gain_network_time"] - 1) < 1e-9
+        if r["same_choice"]:
+            assert r["flopmem"]["n_sliced"] == r["mlp"]["n_sliced"]
+        logs.append(math.log(g))
+    gm = math.exp(sum(logs) / len(logs))
+    assert abs(gm / rec["geomean_gain_network_time"] - 1) < 1e-9
+    assert rec["differing_choices"] == sum(not r["same_choice"] for r in runs)
