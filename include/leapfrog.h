@@ -111,6 +111,11 @@ typedef struct lf_plan_opts {
                                     two more bits of headroom and contracts the rest of the
                                     range again (at most 3 times per call);
                                     LF_OVERFLOW_REPORT returns LF_OVERFLOW at once */
+  int32_t chalf_exec_min_log2;   /* complex-half: the threshold of chalf_min_log2 for the
+                                    execution only (-1 = chalf_min_log2).  The search still
+                                    costs steps with chalf_min_log2, so plans that differ
+                                    only here share their tree and slices while more (or
+                                    fewer) steps run in complex64 */
 } lf_plan_opts;
 
 typedef struct lf_plan_info {
@@ -255,18 +260,22 @@ lf_status lf_debug_scale_slice_leaf(lf_plan* plan, int32_t wire_bit, int32_t val
  * exactly as lf_contract_slices would.  Items of the same plan run in item
  * order (they share that plan's workspace); items of different plans are
  * independent.  mode LF_BATCH_SEQUENTIAL launches every item's kernels on
- * `stream` in item order; LF_BATCH_GRAPH records all items once as one
- * HIP graph, each plan's items a chain and the chains spread over `lanes`
- * parallel branches (1..8; 0 = pick the fastest of 1, 2 and 4 on the first
- * call, timed on temporary accumulators the library allocates and frees,
- * and remember it for this set of plans), and launches it with one
- * hipGraphLaunch on `stream`; the recorded graph is reused while the items
- * are unchanged (and the plans have not been rebound or recalibrated since).
- * Every plan must be bound.  Results are bit-identical between the modes.
- * Saturation gating is as in lf_contract_slices (per plan, in item order);
- * without recalibration: if any item's plan has check_overflow set, the call
- * synchronizes at its end and returns LF_OVERFLOW when such a plan saturated.
- * Otherwise asynchronous.  Errors: as lf_contract_slices.
+ * `stream` in item order.  LF_BATCH_GRAPH groups the items into one chain
+ * per plan, deals the chains to `lanes` lanes by their work (slices times
+ * the plan's time per slice, measured once per plan on `stream` the first
+ * time it is batched, without touching any accumulator; heaviest first onto
+ * the least loaded lane; 1..8, 0 = one lane per plan up to 4), records each
+ * lane once as a HIP
+ * graph, and on every call forks the lanes from `stream`, launches one graph
+ * per lane on a library-owned stream of its own and joins them back into
+ * `stream` (so different plans run concurrently); the recorded graphs are
+ * reused while the items are unchanged (and the plans have not been rebound
+ * or recalibrated since).  Every plan must be bound.  Results are
+ * bit-identical between the modes.  Saturation gating is as in
+ * lf_contract_slices (per plan, in item order); without recalibration: if
+ * any item's plan has check_overflow set, the call synchronizes at its end
+ * and returns LF_OVERFLOW when such a plan saturated.  Otherwise
+ * asynchronous.  Errors: as lf_contract_slices.
  */
 typedef struct lf_batch_item {
   lf_plan* plan;

@@ -52,7 +52,8 @@ class lf_plan_opts(ctypes.Structure):
                 ("launch_mode", ctypes.c_int32), ("check_overflow", ctypes.c_int32),
                 ("slices_per_graph", ctypes.c_int32), ("search_dtype", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("restarts", ctypes.c_int32),
-                ("chalf_headroom_bits", ctypes.c_int32), ("overflow_policy", ctypes.c_int32)]
+                ("chalf_headroom_bits", ctypes.c_int32), ("overflow_policy", ctypes.c_int32),
+                ("chalf_exec_min_log2", ctypes.c_int32)]
 
 
 class lf_overflow_info(ctypes.Structure):

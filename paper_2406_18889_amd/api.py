@@ -56,7 +56,7 @@ class Plan:
                  check_overflow: bool = True, slices_per_graph: int = 8,
                  search_dtype: Optional[str] = None, autotune: bool = True,
                  restarts: int = 1, chalf_headroom_bits: int = 4,
-                 overflow_policy: str = "recalibrate"):
+                 overflow_policy: str = "recalibrate", chalf_exec_min_log2: int = -1):
         lib = _lib.load()
         self._lib = lib
         self._handle = ctypes.c_void_p()
@@ -88,6 +88,7 @@ class Plan:
         opts.restarts = int(restarts)
         opts.chalf_headroom_bits = int(chalf_headroom_bits)
         opts.overflow_policy = OVERFLOW_POLICY[overflow_policy]
+        opts.chalf_exec_min_log2 = int(chalf_exec_min_log2)
         c, arr = _circuit_struct(circuit)
         openq = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         cb = np.ascontiguousarray(self.closed_bits)

@@ -117,6 +117,7 @@ struct PlanOptions {
   int dtype = 0;               // 0 complex64, 1 complex-half
   int search_dtype = 0;        // arithmetic whose step costs the search minimises
   int chalf_min_log2 = 16;     // tensors at least this large run in half
+  int exec_chalf_min_log2 = -1;  // the same for the execution only; -1: chalf_min_log2
   int restarts = 1;            // best candidate trees refined; the ranking cost picks one
   double bytes_per_elem = 8.0;
 };

@@ -862,7 +862,8 @@ std::string plan_network(const Network& net, const PlanOptions& opt, HostPlan& h
     for (int x : kl) s.nk += C.bits_of[x];
     s.variant = (best.e.closure[n] & SL).any();
     int wa = C.weight(As), wb = C.weight(Bs), wc = C.weight(best.e.idx[n].andnot(SL));
-    s.dtype = step_dtype(opt.dtype, opt.chalf_min_log2, wa, wb, wc);
+    s.dtype = step_dtype(opt.dtype, opt.exec_chalf_min_log2 >= 0 ? opt.exec_chalf_min_log2 : opt.chalf_min_log2,
+                         wa, wb, wc);
     s.macs = std::ldexp(1.0, s.nz + s.nm + s.nn + s.nk);
     rev.push_back(s);
   }
