@@ -1325,6 +1325,99 @@ static hipError_t launch_skinny(const GettArgs& a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ launchers
+// ------------------------------------------------------------ long-K MFMA
+// Steps with a small result per batch entry (M, N <= 32 complex) and a long
+// contraction (K >= 128 complex), e.g. the last stem steps that sum a
+// 2^13-long index for each of 256 closed strings: one workgroup of 16 waves
+// per batch entry.  Wave w takes the w-th contiguous sixteenth of K and runs
+// MFMA 32x32x16 on fragments read straight from HBM (each lane 16 bytes of
+// one A row and one B row per k step, four k steps in flight), B' formed in
+// registers as in the DMA tile; the 16 partial 32 x 32 results are summed in
+// LDS in wave order (fixed, so the result is deterministic).  HBM-bound: A
+// and B are read once, the small C written once.
+constexpr int LK_WAVES = 16;
+
+template <typename TO>
+__global__ void __launch_bounds__(64 * LK_WAVES) gett_longk(GettArgs a) {
+  constexpr int U = 4;
+  __shared__ float red[LK_WAVES][32][64];
+  const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
+  const int64_t z = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r = lane & 31, half = lane >> 5;
+  const bool okA = r < M, okB = r < N;
+  const _Float16* A = static_cast<const _Float16*>(a.A);
+  const _Float16* B = static_cast<const _Float16*>(a.B);
+  // 16-byte chunks (4 complex) of row r; chunk 2t + half is this lane's part of k step t
+  const uint4* pa = reinterpret_cast<const uint4*>(A + 2 * ((a.offA ? a.offA[z] : z * M * K) + (okA ? r : 0) * K));
+  const uint4* pb = reinterpret_cast<const uint4*>(B + 2 * ((a.offB ? a.offB[z] : z * N * K) + (okB ? r : 0) * K));
+  const int64_t steps = K / 8, per = steps / LK_WAVES;
+  const int64_t t0 = int64_t(w) * per, t1 = t0 + per;
+  f32x16 accr, acci;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) { accr[v] = 0.0f; acci[v] = 0.0f; }
+  const uint4 zero4 = {0u, 0u, 0u, 0u};
+  auto step = [&](uint4 ra, uint4 rb) __attribute__((always_inline)) {
+    u32x4 x, re, im;
+    x[0] = rb.x; x[1] = rb.y; x[2] = rb.z; x[3] = rb.w;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      re[i] = x[i] ^ 0x80000000u;
+      im[i] = __builtin_amdgcn_alignbit(x[i], x[i], 16);
+    }
+    const f16x8 av = __builtin_bit_cast(f16x8, ra);
+    accr = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, re), av, accr, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, im), av, acci, 0, 0, 0);
+  };
+  int64_t t = t0;
+  for (; t + U <= t1; t += U) {
+    uint4 ra[U], rb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ra[u] = okA ? pa[2 * (t + u) + half] : zero4;
+      rb[u] = okB ? pb[2 * (t + u) + half] : zero4;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) step(ra[u], rb[u]);
+  }
+  for (; t < t1; ++t) step(okA ? pa[2 * t + half] : zero4, okB ? pb[2 * t + half] : zero4);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    red[w][v][lane] = accr[v];
+    red[w][16 + v][lane] = acci[v];
+  }
+  __syncthreads();
+  // thread (v, l): the result of register v of lane l, summed over the waves
+  const int v = tid >> 6, l = tid & 63;
+  float re = 0.0f, im = 0.0f;
+#pragma unroll
+  for (int ww = 0; ww < LK_WAVES; ++ww) {
+    re += red[ww][v][l];
+    im += red[ww][16 + v][l];
+  }
+  re *= a.scale;
+  im *= a.scale;
+  const int m = l & 31, n = 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+  float lmax = 0.0f;
+  unsigned lsat = 0;
+  if (m < M && n < N) {
+    lmax = fmaxf(fabsf(re), fabsf(im));
+    if (!a.amax_only) {
+      const int64_t off = scatter_bits(z, a.cz, a.nz) + scatter_bits(m, a.cm, a.nm) + scatter_bits(n, a.cn, a.nn);
+      lsat = CIO<TO>::store(static_cast<TO*>(a.C), off, re, im);
+    }
+  }
+  block_amax_sat(lmax, lsat, a.amax, a.sat);
+}
+
+template <typename TO>
+static hipError_t launch_longk(const GettArgs& a, hipStream_t s) {
+  const int64_t blocks = int64_t(1) << a.nz;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gett_longk<TO>), dim3(unsigned(blocks)), dim3(64 * LK_WAVES), 0, s, a);
+  return hipGetLastError();
+}
+
 bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
   (void)nz;
   (void)nk;
@@ -1340,6 +1433,8 @@ bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
   // (row * K * 4 bytes within a 256-row panel) that fit 32 bits
   if (kernel == K_MFMA_DMA || kernel == K_MFMA_DMA_X || kernel == K_MFMA_DMA4 || kernel == K_MFMA_DMA4_X)
     return in_dt == 1 && nm >= 8 && nn >= 7 && nk >= 5 && nk <= 21;
+  // at least 8 complex per wave (one k step each)
+  if (kernel == K_LONGK) return in_dt == 1 && nm <= 5 && nn <= 5 && nk >= 7;
   return false;
 }
 
@@ -1383,6 +1478,7 @@ static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
   if (kernel == K_NARROW) return launch_narrow<TI, TI, TO>(a, s);
   if constexpr (std::is_same<TI, _Float16>::value) {
     if (kernel == K_SKINNY) return launch_skinny<_Float16, TO>(a, s);
+    if (kernel == K_LONGK) return launch_longk<TO>(a, s);
   }
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn;
   if (kernel == K_MFMA) {

@@ -93,6 +93,8 @@ SHAPES = [
     (0, 8, 7, 8), (0, 9, 7, 10),
     # more tiles than resident blocks: the persistent 4 x 2 tile loops
     (1, 14, 9, 5), (1, 14, 9, 3),
+    # long K with a small result per batch entry (M, N <= 32): K split over waves
+    (8, 5, 5, 9), (3, 4, 3, 10), (0, 5, 5, 7), (2, 2, 5, 8),
 ]
 
 
@@ -110,6 +112,8 @@ def _applicable(kernel, dt, shape):
         return dt == "chalf" and nn <= 4 and 2 <= nk <= 6 and nm >= (6 if nk == 6 else 7)
     if kernel in (11, 12, 13, 14):
         return dt == "chalf" and nm >= 8 and nn >= 7 and 5 <= nk <= 21
+    if kernel == 15:
+        return dt == "chalf" and nm <= 5 and nn <= 5 and nk >= 7
     return True
 
 
@@ -137,7 +141,7 @@ def _to_half_pairs(x, e):
     return torch.from_numpy(v.astype(np.float16)).cuda()
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_pair_chalf(lf, kernel, shape):
     nz, nm, nn, nk = shape
@@ -255,7 +259,7 @@ def test_pair_mixed_half_a_c64_b(lf, kernel, shape):
 
 
 @pytest.mark.parametrize("kernel,shape", [(1, (0, 7, 5, 6)), (11, (0, 8, 7, 6)), (12, (1, 8, 7, 5)),
-                                          (13, (0, 9, 7, 8)), (14, (1, 8, 8, 5))])
+                                          (13, (0, 9, 7, 8)), (14, (1, 8, 8, 5)), (15, (6, 5, 5, 9))])
 def test_pair_half_in_c64_out(lf, kernel, shape):
     nz, nm, nn, nk = shape
     _say(f"pair half in, c64 out kernel={kernel} shape={shape}")
