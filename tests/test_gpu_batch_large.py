@@ -1,0 +1,94 @@
+"""Sparse output at a large number of closed strings (Methods A and D: the
+paper computes 2^10 correlated amplitudes for each of 3 million sampled
+strings in every subtask): the 30-qubit, 14-cycle circuit with 2^20 closed
+strings x 2^6 open values (2^26 amplitudes) in one plan, all 2^8 slices
+summed, through the C ABI.
+
+* 1024 of the 2^20 strings (drawn once, seeded) against the oracle's state
+  vector (stored values): complex64 to 1e-5, complex-half to 5e-3 with
+  fidelity >= 0.999;
+* the global top-2^15 over all 2^26 candidates and the top-1 of 4096 of the
+  groups, bit-exact against the oracle's selection on the same amplitudes.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import topk
+
+pytestmark = [pytest.mark.gpu]
+
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+HAVE = os.path.exists(os.path.join(GOLD, "rqc30_batch_sample.npz"))
+
+
+def _say(msg):
+    sys.stdout.write(msg + "\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_18889_amd as lf
+    from paper_2406_18889_amd import _lib
+    _lib.load()
+    return lf
+
+
+def rel_err(a, ref):
+    a = np.asarray(a).reshape(-1)
+    ref = np.asarray(ref).reshape(-1)
+    return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+
+
+def fidelity(a, ref):
+    a = np.asarray(a).reshape(-1)
+    ref = np.asarray(ref).reshape(-1)
+    return float(abs(np.vdot(ref, a)) ** 2 / (np.vdot(a, a).real * np.vdot(ref, ref).real))
+
+
+@pytest.mark.skipif(not HAVE, reason="stored large-batch values not generated")
+@pytest.mark.parametrize("dtype", ["c64", "chalf"])
+def test_rqc30_million_strings(lf, dtype):
+    circ, openq, cb, spec = wl.standard_workload("rqc30")
+    closed = wl.closed_bitstrings(circ.n_qubits, openq, wl.XEB_MCMC_STRINGS, seed=wl.XEB_MCMC_SEED)
+    st = np.load(os.path.join(GOLD, "rqc30_batch_sample.npz"))
+    plan = lf.Plan(circ, openq, closed, dtype=dtype, max_log2=28, sliced_wires=wl.RQC30_SLICED_WIRES,
+                   sa_iters=1_000_000, restarts=4, check_overflow=True, overflow_policy="report")
+    info = plan.info()
+    _say(f"{dtype}: {info['n_batch']} strings, {info['n_slices']} slices of "
+         f"{info['macs_per_slice']:.3g} multiply-adds, workspace {info['workspace_bytes'] / 2**30:.1f} GiB")
+    plan.bind()
+    amps = plan.contract(0, info["n_slices"])
+    torch.cuda.synchronize()
+    rows = torch.from_numpy(st["rows"]).cuda()
+    got = amps[rows].cpu().numpy()
+    e, f = rel_err(got, st["amps"]), fidelity(got, st["amps"])
+    _say(f"{dtype}: 1024 strings against the oracle: rel_err {e:.2e} fidelity {f:.6f}")
+    assert e < (1e-5 if dtype == "c64" else 5e-3)
+    if dtype == "chalf":
+        assert f >= 0.999
+    n = amps.numel()
+    idx, prob = lf.postselect_topk(amps, n, 1 << 15)
+    g1, p1 = lf.postselect_topk(amps, 64, 1)
+    torch.cuda.synchronize()
+    host = amps.cpu().numpy().reshape(-1)
+    i_ref, p_ref = topk.topk(host, n, 1 << 15)
+    assert np.array_equal(idx.cpu().numpy(), i_ref)
+    assert np.array_equal(prob.cpu().numpy().view(np.uint64), p_ref.view(np.uint64))
+    pick = np.random.Generator(np.random.PCG64(3)).choice(closed.size, 4096, replace=False)
+    sub = host.reshape(closed.size, 64)[pick]
+    i1, q1 = topk.topk(sub, 64, 1)
+    assert np.array_equal(g1.cpu().numpy()[pick], i1)
+    assert np.array_equal(p1.cpu().numpy()[pick], q1)
+    plan.workspace = None
+    plan.close()
+    torch.cuda.empty_cache()

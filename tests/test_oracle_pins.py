@@ -339,3 +339,49 @@ def test_probs_and_moments_on_known_states():
     assert np.array_equal(sv.probs(v), topk.probabilities(v))
     assert abs(m2 - (0.36 ** 2 + 0.64 ** 2)) < 1e-15
     assert abs(m3 - (0.36 ** 3 + 0.64 ** 3)) < 1e-15
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(os.path.dirname(__file__), "golden", "rqc30_xeb.json")),
+                    reason="stored XEB study values not generated")
+def test_rqc30_stored_xeb_study():
+    """The oracle's own 30-qubit XEB study (written by tests/golden/make_rqc30.py
+    from state vectors only) against the paper's predictions:
+      - top-k XEB of the fraction-2^-D prefix state, k = 2^8..2^15 of 2^30
+        (Eq. 4): F ln(N/k) with F the prefix's fidelity.  Eq. 4 is the exact
+        expectation when the approximate state is the fidelity-F mixture of
+        the exact state with an independent random state (Appendix A's
+        model: then E[Nq | Np] = F Np + 1 - F and the top k of Np average
+        1 + ln(N/k)); a sliced prefix is not exactly such a mixture, so the
+        pin allows 15% of F ln(N/k) for the model's error (the paper's own
+        amplifications scatter by 2.5%, 10.4694 +- 0.2635) plus 4 standard
+        deviations of the mean of k values of Nq under the model,
+        sqrt((F^2 + (1-F)^2 + 2F(1-F)(1 + ln(N/k))) / k);
+      - averaged over D = 1..5, top-2^15 XEB / F against the paper's printed
+        10.4694 +- 0.2635 and ln 2^15 = 10.3972 (three printed deviations);
+      - the XEB of sampling from the approximate p over the 2^26 candidates
+        (Eq. 3): F within 25% for D = 1..4 (the paper's Fig. 3 agreement), and
+        0 < XEB for D = 5."""
+    import json
+    gold = os.path.join(os.path.dirname(__file__), "golden")
+    with open(os.path.join(gold, "rqc30_xeb.json")) as f:
+        st = json.load(f)
+    with open(os.path.join(gold, "rqc30_prefix.json")) as f:
+        fid = json.load(f)
+    N = st["n_candidates_topk"]
+    assert N == 2 ** 30 and st["k_values"] == [2 ** e for e in range(8, 16)]
+    ratios = []
+    for D in range(1, 6):
+        F = fid[f"fidelity_D{D}"]
+        for k, x in zip(st["k_values"], st[f"xeb_topk_D{D}"]):
+            L = math.log(N / k)
+            sd = math.sqrt((F * F + (1 - F) ** 2 + 2 * F * (1 - F) * (1 + L)) / k)
+            assert abs(x - F * L) <= 0.15 * F * L + 4 * sd, (D, k, x, F * L, sd)
+        ratios.append(st[f"xeb_topk_D{D}"][-1] / F)
+        m = st[f"mcmc_xeb_expect_D{D}"]
+        if D <= 4:
+            assert abs(m / F - 1.0) < 0.25, (D, m, F)
+        else:
+            assert m > 0
+    mean = float(np.mean(ratios))
+    assert abs(mean - 10.4694) <= 3 * 0.2635
+    assert abs(mean - math.log(2 ** 15)) <= 3 * 0.2635

@@ -25,4 +25,7 @@ from .circuits import (  # noqa: F401
     WORKLOADS,
     random_complex,
     mixed_workload,
+    RQC30_SLICED_WIRES,
+    XEB_MCMC_STRINGS,
+    XEB_MCMC_SEED,
 )

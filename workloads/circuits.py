@@ -218,6 +218,14 @@ WORKLOADS = {
     "rqc53": dict(rows=6, cols=9, cycles=20, n_removed=1, n_open=10, n_batch=256,
                   n_sliced=-1, max_log2=28),
 }
+# The eight sliced wires (qubit, j) of the 30-qubit workload, wire t being
+# bit t of the slice index (the set the planner picks for it at a
+# 2^26-element cap); the slice prefix [0, 2^(8-D)) is the fraction 2^-D.
+RQC30_SLICED_WIRES = [(19, 9), (20, 9), (21, 9), (14, 7), (22, 9), (24, 5), (15, 7), (25, 7)]
+# candidate set of the 30-qubit sampling study: 2^20 closed strings (seeded)
+# times the 64 values of the open qubits
+XEB_MCMC_STRINGS = 1 << 20
+XEB_MCMC_SEED = 2024
 CIRCUIT_SEED = 2406
 BITSTRING_SEED = 18889
 REMOVAL_SEED = 53
