@@ -1369,18 +1369,30 @@ __global__ void __launch_bounds__(64 * LK_WAVES) gett_longk(GettArgs a) {
     accr = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, re), av, accr, 0, 0, 0);
     acci = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, im), av, acci, 0, 0, 0);
   };
-  int64_t t = t0;
-  for (; t + U <= t1; t += U) {
-    uint4 ra[U], rb[U];
+  // groups of U k steps, the loads of group g + 1 issued before the MFMAs of
+  // group g (two register sets), so that two groups are in flight
+  uint4 ra[2][U], rb[2][U];
+  auto load = [&](int set, int64_t t) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ra[u] = okA ? pa[2 * (t + u) + half] : zero4;
-      rb[u] = okB ? pb[2 * (t + u) + half] : zero4;
+      ra[set][u] = okA ? pa[2 * (t + u) + half] : zero4;
+      rb[set][u] = okB ? pb[2 * (t + u) + half] : zero4;
     }
+  };
+  const int64_t groups = per / U;
+  if (groups > 0) load(0, t0);
+  for (int64_t g = 0; g < groups; g += 2) {
+    if (g + 1 < groups) load(1, t0 + (g + 1) * U);
 #pragma unroll
-    for (int u = 0; u < U; ++u) step(ra[u], rb[u]);
+    for (int u = 0; u < U; ++u) step(ra[0][u], rb[0][u]);
+    if (g + 1 < groups) {
+      if (g + 2 < groups) load(0, t0 + (g + 2) * U);
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(ra[1][u], rb[1][u]);
+    }
   }
-  for (; t < t1; ++t) step(okA ? pa[2 * t + half] : zero4, okB ? pb[2 * t + half] : zero4);
+  for (int64_t t = t0 + groups * U; t < t1; ++t)
+    step(okA ? pa[2 * t + half] : zero4, okB ? pb[2 * t + half] : zero4);
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     red[w][v][lane] = accr[v];

@@ -61,8 +61,11 @@ def test_rqc30_million_strings(lf, dtype):
     circ, openq, cb, spec = wl.standard_workload("rqc30")
     closed = wl.closed_bitstrings(circ.n_qubits, openq, wl.XEB_MCMC_STRINGS, seed=wl.XEB_MCMC_SEED)
     st = np.load(os.path.join(GOLD, "rqc30_batch_sample.npz"))
-    plan = lf.Plan(circ, openq, closed, dtype=dtype, max_log2=28, sliced_wires=wl.RQC30_SLICED_WIRES,
-                   sa_iters=1_000_000, restarts=4, check_overflow=True, overflow_policy="report")
+    # both arithmetics search with the complex64 step costs (one tree; the
+    # complex-half costs lead this search to no tree within the cap)
+    plan = lf.Plan(circ, openq, closed, dtype=dtype, search_dtype="c64", max_log2=28,
+                   sliced_wires=wl.RQC30_SLICED_WIRES, sa_iters=1_000_000, restarts=4,
+                   check_overflow=True, overflow_policy="report")
     info = plan.info()
     _say(f"{dtype}: {info['n_batch']} strings, {info['n_slices']} slices of "
          f"{info['macs_per_slice']:.3g} multiply-adds, workspace {info['workspace_bytes'] / 2**30:.1f} GiB")
