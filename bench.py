@@ -30,7 +30,7 @@ KERNEL_NAMES = {0: "gett_thin", 1: "gett_mfma", 2: "gett_mfma_big<4,2,2,1,32,0>"
                 8: "gett_mfma_big<4,2,2,1,32,1>", 9: "gett_mfma_big<4,4,1,2,32,1>",
                 10: "gett_mfma_big<4,4,1,1,32,1>", 11: "gett_mfma_dma<0,8>", 12: "gett_mfma_dma<1,8>",
                 13: "gett_mfma_dma<0,4>", 14: "gett_mfma_dma<1,4>",
-                15: "gett_longk"}
+                15: "gett_longk", 16: "gett_mfma_dma<0,4,128,2>", 17: "gett_mfma_dma<1,4,128,2>"}
 # planner settings per workload (search effort, not inputs)
 PLAN_OPTS = {"rqc53": {"sa_iters": 4_000_000, "restarts": 8, "chalf_exec_min_log2": 22}}
 # the kernel choices (step shape and operand types -> kernel variant) the

@@ -402,7 +402,9 @@ lf_status lf_plan_kernel_times(lf_plan* plan, double* total_ms, int64_t* launche
  * kernel 11 with the XCD-grouped tile order, 13 and 14 kernels 11 and 12 on
  * four waves (one per SIMD), 15 one sixteen-wave workgroup per batch entry
  * with K split over the waves (complex-half, nm <= 5, nn <= 5, nk >= 7),
- * -1 the default choice; a kernel that does
+ * 16 and 17 the 128 x 128 tile of kernel 11 on four waves with two operand
+ * stages, two workgroups per CU (complex-half, 2^nm and 2^nn multiples of
+ * 128, 5 <= nk <= 21), in the two tile orders, -1 the default choice; a kernel that does
  * not apply to the
  * shape or dtype falls back to 0.  Device pointers owned by the caller; A and
  * B 16-byte aligned.  Limits: nz <= 20, nm, nn <= 40.  Errors:

@@ -56,10 +56,14 @@ struct GettArgs {
 // less HBM traffic when an A panel would otherwise be fetched by every XCD.
 // K_LONGK: M, N <= 32 complex and K >= 128: one 16-wave workgroup per batch
 // entry, K split over the waves, complex-half only.
+// K_MFMA_DMA2, K_MFMA_DMA2_X: the 128 x 128 tile of the DMA-fed kernel on
+// four waves with two operand stages (two workgroups per CU), both tile
+// orders; whole tiles (M % 128, N % 128, K % 32 == 0).
 enum KernelId : int {
   K_THIN = 0, K_MFMA = 1, K_MFMA_BIG = 2, K_NARROW = 3, K_MFMA_WIDE = 4, K_MFMA_DB = 5, K_MFMA_DEEP = 6,
   K_SKINNY = 7, K_MFMA_BIG_X = 8, K_MFMA_DB_X = 9, K_MFMA_WIDE_X = 10, K_MFMA_DMA = 11,
-  K_MFMA_DMA_X = 12, K_MFMA_DMA4 = 13, K_MFMA_DMA4_X = 14, K_LONGK = 15, K_COUNT = 16
+  K_MFMA_DMA_X = 12, K_MFMA_DMA4 = 13, K_MFMA_DMA4_X = 14, K_LONGK = 15, K_MFMA_DMA2 = 16,
+  K_MFMA_DMA2_X = 17, K_COUNT = 18
 };
 
 // a_dt, b_dt, out_dt: 0 complex64 (float pairs), 1 complex-half (_Float16

@@ -824,9 +824,7 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
 // issued from inline assembly: the compiler's own form of this load makes it
 // wait for every outstanding load before any LDS access.  Here the waits are
 // explicit (see the main loop).
-constexpr int DMA_BM = 256, DMA_BN = 128, DMA_BK = 32;
-constexpr int DMA_SA = DMA_BM * 128;                  // bytes of the A tile of a stage
-constexpr int DMA_STAGE = (DMA_BM + DMA_BN) * 128;    // bytes per stage
+constexpr int DMA_BM = 256, DMA_BN = 128, DMA_BK = 32;   // default tile (the m side may be 128)
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -841,8 +839,9 @@ __device__ __forceinline__ void dma_load16(uint32_t voff, const void* sbase, uin
 // may still be in flight)
 template <int N>
 __device__ __forceinline__ void wait_loads_barrier() {
-  static_assert(N == 0 || N == 6 || N == 8 || N == 12 || N == 15, "vmcnt immediate");
+  static_assert(N == 0 || N == 2 || N == 6 || N == 8 || N == 12 || N == 15, "vmcnt immediate");
   if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 2) asm volatile("s_waitcnt vmcnt(2) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   if constexpr (N == 6) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   if constexpr (N == 8) asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   if constexpr (N == 12) asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");
@@ -854,29 +853,42 @@ __device__ __forceinline__ void wait_loads_barrier() {
 // 64 n, 16 MFMAs per k step, 256 accumulator registers (AGPRs): fewer LDS
 // bytes and VALU operations per MFMA, and the waits must be hidden by the
 // order of one wave's instructions alone.
-template <typename TO, int ORDER, int NW>
-__global__ void __launch_bounds__(64 * NW, 1) gett_mfma_dma(GettArgs a) {
+//
+// BM = 128, STAGES = 2 (kernels 16 and 17): the 128 m x 128 n tile on four
+// waves (each 64 m x 64 n, as in the eight-wave form) with two operand
+// stages, so that its LDS (68 KB) lets two workgroups share a CU: one
+// workgroup's first loads and write-out run while the other computes, which
+// pays on steps with a short K where those fixed costs are a large share.
+// With two stages the loads of tile t+1 are issued during tile t and waited
+// for before its last k step (the co-resident workgroup covers that wait).
+template <typename TO, int ORDER, int NW, int BM = DMA_BM, int STAGES = 3>
+__global__ void __launch_bounds__(64 * NW, STAGES == 2 ? 2 : 1) gett_mfma_dma(GettArgs a) {
   static_assert(NW == 4 || NW == 8, "wave count");
+  static_assert((BM == 256 && STAGES == 3) || (BM == 128 && STAGES == 2 && NW == 4), "tile forms");
   constexpr int NT = 64 * NW;
-  constexpr int WM = NW == 8 ? 2 : 4, WN = 2;   // 32 x 32 MFMA tiles per wave in m and complex n
-  constexpr int MW = DMA_BM / (32 * WM);         // waves along m
-  constexpr int A_LOADS = DMA_BM * 128 / 1024 / NW, B_LOADS = DMA_BN * 128 / 1024 / NW;
+  constexpr int MW = NW / 2;                     // waves along m (two along n)
+  constexpr int WM = BM / (32 * MW), WN = 2;     // 32 x 32 MFMA tiles per wave in m and complex n
+  constexpr int SA = BM * 128;                   // bytes of the A tile of a stage
+  constexpr int STAGE = (BM + DMA_BN) * 128;     // bytes per stage
+  constexpr int A_LOADS = BM * 128 / 1024 / NW, B_LOADS = DMA_BN * 128 / 1024 / NW;
   constexpr int LOADS = A_LOADS + B_LOADS;       // per wave per stage
   constexpr int CHUNK = (LOADS + 3) / 4;         // loads of a tile issued per k step
-  static_assert(MW * 2 == NW && LOADS * NW * 1024 == DMA_STAGE, "wave grid and loads");
-  __shared__ __attribute__((aligned(1024))) unsigned char smem[3 * DMA_STAGE];
-  __shared__ int64_t cmT[DMA_BM];
+  static_assert(WM * 32 * MW == BM && LOADS * NW * 1024 == STAGE, "wave grid and loads");
+  // operand stages, reused for the staged result tile at the end
+  constexpr int SMEM = (STAGES * STAGE > BM * (DMA_BN + 1) * 4 ? STAGES * STAGE : BM * (DMA_BN + 1) * 4);
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[(SMEM + 1023) / 1024 * 1024];
+  __shared__ int64_t cmT[BM];
   __shared__ int64_t cnT[DMA_BN];
 
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
-  const int64_t mt = M / DMA_BM, nt = N / DMA_BN;
+  const int64_t mt = M / BM, nt = N / DMA_BN;
   int64_t z, tm, tn;
   big_tile_of(blockIdx.x, gridDim.x, ORDER, mt, nt, z, tm, tn);
-  const int64_t m0 = tm * DMA_BM, n0 = tn * DMA_BN;
+  const int64_t m0 = tm * BM, n0 = tn * DMA_BN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = w % MW, wn = w / MW;
-  for (int i = tid; i < DMA_BM; i += NT) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
+  for (int i = tid; i < BM; i += NT) cmT[i] = scatter_bits(m0 + i, a.cm, a.nm);
   for (int i = tid; i < DMA_BN; i += NT) cnT[i] = scatter_bits(n0 + i, a.cn, a.nn);
   const int64_t czv = scatter_bits(z, a.cz, a.nz);
   const unsigned char* Ab =
@@ -904,13 +916,13 @@ __global__ void __launch_bounds__(64 * NW, 1) gett_mfma_dma(GettArgs a) {
     constexpr int g = decltype(G)::value;
     const unsigned char* ga = Ab + t * (DMA_BK * 4);
     const unsigned char* gb = Bb + t * (DMA_BK * 4);
-    const uint32_t base = lds0 + uint32_t(st) * DMA_STAGE;
+    const uint32_t base = lds0 + uint32_t(st) * STAGE;
 #pragma unroll
     for (int i = g * CHUNK; i < (g + 1) * CHUNK && i < LOADS; ++i) {
       if (i < A_LOADS) dma_load16(voA[i < A_LOADS ? i : 0], ga, base + uint32_t(w * A_LOADS + i) * 1024u);
       else
         dma_load16(voB[i < A_LOADS ? 0 : i - A_LOADS], gb,
-                   base + DMA_SA + uint32_t(w * B_LOADS + i - A_LOADS) * 1024u);
+                   base + SA + uint32_t(w * B_LOADS + i - A_LOADS) * 1024u);
     }
   };
   using I0 = std::integral_constant<int, 0>;
@@ -928,7 +940,7 @@ __global__ void __launch_bounds__(64 * NW, 1) gett_mfma_dma(GettArgs a) {
 #pragma unroll
   for (int bn = 0; bn < WN; ++bn) {
     const int r = wn * 32 * WN + bn * 32 + (lane & 31);
-    offB[bn] = DMA_SA + r * 128;
+    offB[bn] = SA + r * 128;
     swB[bn] = (r >> 1) & 7;
   }
   f16x8 af[2][WM];
@@ -1026,49 +1038,82 @@ __global__ void __launch_bounds__(64 * NW, 1) gett_mfma_dma(GettArgs a) {
   issue_group(I1{}, 0, 0);
   issue_group(I2{}, 0, 0);
   issue_group(I3{}, 0, 0);
-  if (T > 1) {
-    issue_group(I0{}, 1, 1);
-    issue_group(I1{}, 1, 1);
-    issue_group(I2{}, 1, 1);
-    issue_group(I3{}, 1, 1);
+  if constexpr (STAGES == 3) {
+    if (T > 1) {
+      issue_group(I0{}, 1, 1);
+      issue_group(I1{}, 1, 1);
+      issue_group(I2{}, 1, 1);
+      issue_group(I3{}, 1, 1);
+    }
+    if (T > 2) issue_group(I0{}, 2, 2);
+    // tile 0 has landed: only tile 1 and the first group of tile 2 may be in flight
+    if (T > 2) wait_loads_barrier<LOADS + CHUNK>();
+    else if (T > 1) wait_loads_barrier<LOADS>();
+    else wait_loads_barrier<0>();
+  } else {
+    if (T > 1) issue_group(I0{}, 1, 1);
+    // tile 0 has landed: only the first group of tile 1 may be in flight
+    if (T > 1) wait_loads_barrier<CHUNK>();
+    else wait_loads_barrier<0>();
   }
-  if (T > 2) issue_group(I0{}, 2, 2);
-  // tile 0 has landed: only tile 1 and the first group of tile 2 may be in flight
-  if (T > 2) wait_loads_barrier<LOADS + CHUNK>();
-  else if (T > 1) wait_loads_barrier<LOADS>();
-  else wait_loads_barrier<0>();
   frags(smem, 0, 0);
   f16x8 bfe[WN][2], bfo[WN][2];   // B' operands of even and odd k steps
   bprime(I0{}, bfe);
   int st = 0;
   for (int64_t t = 0; t + 1 < T; ++t) {
-    const unsigned char* s = smem + st * DMA_STAGE;
-    const int nst = st == 2 ? 0 : st + 1, pst = st == 0 ? 2 : st - 1;   // stages of t+1, t+2
-    const bool more = t + 2 < T;
-    if (more) issue_group(I1{}, pst, t + 2);
-    __builtin_amdgcn_sched_barrier(0);
-    kstep(I0{}, bfe, bfo, s, 8);
-    __builtin_amdgcn_sched_barrier(0);
-    if (more) issue_group(I2{}, pst, t + 2);
-    __builtin_amdgcn_sched_barrier(0);
-    kstep(I1{}, bfo, bfe, s, 16);
-    __builtin_amdgcn_sched_barrier(0);
-    if (more) issue_group(I3{}, pst, t + 2);
-    __builtin_amdgcn_sched_barrier(0);
-    kstep(I0{}, bfe, bfo, s, 24);
-    __builtin_amdgcn_sched_barrier(0);
-    // tile t+1 has landed (only tile t+2's loads may be in flight) and every
-    // wave's reads of tile t have returned: stage st is free
-    if (more) wait_loads_barrier<LOADS>();
-    else wait_loads_barrier<0>();
-    if (t + 3 < T) issue_group(I0{}, st, t + 3);
-    __builtin_amdgcn_sched_barrier(0);
-    kstep(I1{}, bfo, bfe, smem + nst * DMA_STAGE, 0);
-    __builtin_amdgcn_sched_barrier(0);
-    st = nst;
+    const unsigned char* s = smem + st * STAGE;
+    if constexpr (STAGES == 3) {
+      const int nst = st == 2 ? 0 : st + 1, pst = st == 0 ? 2 : st - 1;   // stages of t+1, t+2
+      const bool more = t + 2 < T;
+      if (more) issue_group(I1{}, pst, t + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      kstep(I0{}, bfe, bfo, s, 8);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) issue_group(I2{}, pst, t + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      kstep(I1{}, bfo, bfe, s, 16);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) issue_group(I3{}, pst, t + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      kstep(I0{}, bfe, bfo, s, 24);
+      __builtin_amdgcn_sched_barrier(0);
+      // tile t+1 has landed (only tile t+2's loads may be in flight) and every
+      // wave's reads of tile t have returned: stage st is free
+      if (more) wait_loads_barrier<LOADS>();
+      else wait_loads_barrier<0>();
+      if (t + 3 < T) issue_group(I0{}, st, t + 3);
+      __builtin_amdgcn_sched_barrier(0);
+      kstep(I1{}, bfo, bfe, smem + nst * STAGE, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      st = nst;
+    } else {
+      // tile t+1 goes into the other stage during the first three k steps of
+      // tile t (its first group was issued before); tile t+2 into this stage
+      // once every wave has passed the barrier before the last k step
+      const int nst = st ^ 1;
+      issue_group(I1{}, nst, t + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      kstep(I0{}, bfe, bfo, s, 8);
+      __builtin_amdgcn_sched_barrier(0);
+      issue_group(I2{}, nst, t + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      kstep(I1{}, bfo, bfe, s, 16);
+      __builtin_amdgcn_sched_barrier(0);
+      issue_group(I3{}, nst, t + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      kstep(I0{}, bfe, bfo, s, 24);
+      __builtin_amdgcn_sched_barrier(0);
+      // tile t+1 has landed and every wave's reads of tile t have returned
+      wait_loads_barrier<0>();
+      if (t + 2 < T) issue_group(I0{}, st, t + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      kstep(I1{}, bfo, bfe, smem + nst * STAGE, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      st = nst;
+    }
   }
   {
-    const unsigned char* s = smem + st * DMA_STAGE;
+    const unsigned char* s = smem + st * STAGE;
     kstep(I0{}, bfe, bfo, s, 8);
     kstep(I1{}, bfo, bfe, s, 16);
     kstep(I0{}, bfe, bfo, s, 24);
@@ -1081,10 +1126,10 @@ __global__ void __launch_bounds__(64 * NW, 1) gett_mfma_dma(GettArgs a) {
   if constexpr (std::is_same<TO, _Float16>::value) {
     // staged write-out in the order of the output's strides (as in the
     // large kernels): NT threads, PER elements each
-    constexpr int BM = DMA_BM, BN = DMA_BN, SROW = BN + 1, LM = 8, LN = 7, LT = LM + LN;
+    constexpr int BN = DMA_BN, SROW = BN + 1, LM = BM == 256 ? 8 : 7, LN = 7, LT = LM + LN;
     constexpr int LO = NW == 8 ? 9 : 8, PER = (BM * BN) / NT;
     static_assert((1 << LO) == NT && PER <= NT, "thread bits of the write-out");
-    static_assert(BM * SROW * 4 <= 3 * DMA_STAGE, "staged tile fits the operand stages");
+    static_assert(BM * SROW * 4 <= int(sizeof(smem)), "staged tile fits the operand stages");
     uint32_t* stage = reinterpret_cast<uint32_t*>(smem);
     __shared__ int64_t sStv[LT];   // the tile's bit strides in ascending order (stable)
     __shared__ int sBit[LT];       // and which tile bit each is
@@ -1445,6 +1490,7 @@ bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
   // (row * K * 4 bytes within a 256-row panel) that fit 32 bits
   if (kernel == K_MFMA_DMA || kernel == K_MFMA_DMA_X || kernel == K_MFMA_DMA4 || kernel == K_MFMA_DMA4_X)
     return in_dt == 1 && nm >= 8 && nn >= 7 && nk >= 5 && nk <= 21;
+  if (kernel == K_MFMA_DMA2 || kernel == K_MFMA_DMA2_X) return in_dt == 1 && nm >= 7 && nn >= 7 && nk >= 5 && nk <= 21;
   // at least 8 complex per wave (one k step each)
   if (kernel == K_LONGK) return in_dt == 1 && nm <= 5 && nn <= 5 && nk >= 7;
   return false;
@@ -1475,12 +1521,12 @@ static hipError_t launch_big(const GettArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename TO, int ORDER, int NW>
+template <typename TO, int ORDER, int NW, int BM = DMA_BM, int STAGES = 3>
 static hipError_t launch_dma(const GettArgs& a, hipStream_t s) {
-  if (a.nm < 8 || a.nn < 7 || a.nk < 5 || a.nk > 21) return hipErrorInvalidValue;
-  const int64_t blocks = (int64_t(1) << a.nz) * ((int64_t(1) << a.nm) / DMA_BM) * ((int64_t(1) << a.nn) / DMA_BN);
+  if (a.nm < (BM == 256 ? 8 : 7) || a.nn < 7 || a.nk < 5 || a.nk > 21) return hipErrorInvalidValue;
+  const int64_t blocks = (int64_t(1) << a.nz) * ((int64_t(1) << a.nm) / BM) * ((int64_t(1) << a.nn) / DMA_BN);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gett_mfma_dma<TO, ORDER, NW>), dim3(unsigned(blocks)), dim3(64 * NW), 0, s, a);
+  hipLaunchKernelGGL((gett_mfma_dma<TO, ORDER, NW, BM, STAGES>), dim3(unsigned(blocks)), dim3(64 * NW), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1503,6 +1549,8 @@ static hipError_t launch_typed(int kernel, const GettArgs& a, hipStream_t s) {
       if (kernel == K_MFMA_DMA_X) return launch_dma<TO, 1, 8>(a, s);
       if (kernel == K_MFMA_DMA4) return launch_dma<TO, 0, 4>(a, s);
       if (kernel == K_MFMA_DMA4_X) return launch_dma<TO, 1, 4>(a, s);
+      if (kernel == K_MFMA_DMA2) return launch_dma<TO, 0, 4, 128, 2>(a, s);
+      if (kernel == K_MFMA_DMA2_X) return launch_dma<TO, 1, 4, 128, 2>(a, s);
       if (kernel == K_MFMA_BIG_X) return launch_big<TO, 4, 2, 2, 1, 32, 1>(a, s);
       if (kernel == K_MFMA_DB_X) return launch_big<TO, 4, 4, 1, 2, 32, 1>(a, s);
       if (kernel == K_MFMA_WIDE_X) return launch_big<TO, 4, 4, 1, 1, 32, 1>(a, s);

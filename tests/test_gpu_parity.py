@@ -95,6 +95,8 @@ SHAPES = [
     (1, 14, 9, 5), (1, 14, 9, 3),
     # long K with a small result per batch entry (M, N <= 32): K split over waves
     (8, 5, 5, 9), (3, 4, 3, 10), (0, 5, 5, 7), (2, 2, 5, 8),
+    # the 128 x 128 two-stage tile: one m tile, one and two k tiles
+    (1, 7, 7, 5), (2, 7, 8, 6),
 ]
 
 
@@ -114,6 +116,8 @@ def _applicable(kernel, dt, shape):
         return dt == "chalf" and nm >= 8 and nn >= 7 and 5 <= nk <= 21
     if kernel == 15:
         return dt == "chalf" and nm <= 5 and nn <= 5 and nk >= 7
+    if kernel in (16, 17):
+        return dt == "chalf" and nm >= 7 and nn >= 7 and 5 <= nk <= 21
     return True
 
 
@@ -141,7 +145,7 @@ def _to_half_pairs(x, e):
     return torch.from_numpy(v.astype(np.float16)).cuda()
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_pair_chalf(lf, kernel, shape):
     nz, nm, nn, nk = shape
@@ -186,7 +190,7 @@ def _layout_strides(kind, nz, nm, nn):
     return st
 
 
-@pytest.mark.parametrize("kernel", [2, 5, 8, 11, 12, 13, 14])
+@pytest.mark.parametrize("kernel", [2, 5, 8, 11, 12, 13, 14, 16, 17])
 @pytest.mark.parametrize("layout", ["n_fastest", "m_fastest", "z_fastest", "split_pair"])
 def test_pair_chalf_layouts(lf, kernel, layout):
     nz, nm, nn, nk = 1, 9, 8, 6
@@ -259,7 +263,8 @@ def test_pair_mixed_half_a_c64_b(lf, kernel, shape):
 
 
 @pytest.mark.parametrize("kernel,shape", [(1, (0, 7, 5, 6)), (11, (0, 8, 7, 6)), (12, (1, 8, 7, 5)),
-                                          (13, (0, 9, 7, 8)), (14, (1, 8, 8, 5)), (15, (6, 5, 5, 9))])
+                                          (13, (0, 9, 7, 8)), (14, (1, 8, 8, 5)), (15, (6, 5, 5, 9)),
+                                          (16, (1, 7, 7, 6)), (17, (0, 8, 7, 9))])
 def test_pair_half_in_c64_out(lf, kernel, shape):
     nz, nm, nn, nk = shape
     _say(f"pair half in, c64 out kernel={kernel} shape={shape}")
