@@ -58,6 +58,7 @@ enum { LF_C64 = 0, LF_CHALF = 1 };          /* contraction arithmetic */
 enum { LF_COST_FLOPMEM = 0, LF_COST_MLP = 1 }; /* path-search cost model */
 enum { LF_LAUNCH_STREAM = 0, LF_LAUNCH_GRAPH = 1 };
 enum { LF_OVERFLOW_RECALIBRATE = 0, LF_OVERFLOW_REPORT = 1 }; /* complex-half saturation policy */
+enum { LF_MULT_AUTO = 0, LF_MULT_4M = 1, LF_MULT_3M = 2 };    /* real products per complex product */
 
 typedef struct lf_gate {
   int32_t n_q;       /* 1 or 2 */
@@ -116,6 +117,17 @@ typedef struct lf_plan_opts {
                                     costs steps with chalf_min_log2, so plans that differ
                                     only here share their tree and slices while more (or
                                     fewer) steps run in complex64 */
+  int32_t mult;                  /* LF_MULT_AUTO or LF_MULT_4M: every complex product is
+                                    four real products on MFMA (the real and imaginary
+                                    parts of C as two real GEMMs over 2K against operand
+                                    forms of B made in registers).  LF_MULT_3M is
+                                    rejected (LF_INVALID_ARGUMENT): it would need the sums
+                                    Ar + Ai and Br + Bi as extra operand tensors and loses
+                                    bits to cancellation in complex-half */
+  const char* autotune_cache;    /* NULL, or a file of kernel choices (lf_autotune_save
+                                    format): merged into the process's choices when the
+                                    plan is built (if the file exists) and rewritten with
+                                    them after the plan's first contraction has tuned */
 } lf_plan_opts;
 
 typedef struct lf_plan_info {

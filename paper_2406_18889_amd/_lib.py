@@ -29,6 +29,9 @@ LF_LAUNCH_STREAM = 0
 LF_LAUNCH_GRAPH = 1
 LF_OVERFLOW_RECALIBRATE = 0
 LF_OVERFLOW_REPORT = 1
+LF_MULT_AUTO = 0
+LF_MULT_4M = 1
+LF_MULT_3M = 2
 LF_N_FEATURES = 14
 
 
@@ -53,7 +56,8 @@ class lf_plan_opts(ctypes.Structure):
                 ("slices_per_graph", ctypes.c_int32), ("search_dtype", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("chalf_headroom_bits", ctypes.c_int32), ("overflow_policy", ctypes.c_int32),
-                ("chalf_exec_min_log2", ctypes.c_int32)]
+                ("chalf_exec_min_log2", ctypes.c_int32), ("mult", ctypes.c_int32),
+                ("autotune_cache", ctypes.c_char_p)]
 
 
 class lf_overflow_info(ctypes.Structure):

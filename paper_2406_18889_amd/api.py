@@ -56,7 +56,8 @@ class Plan:
                  check_overflow: bool = True, slices_per_graph: int = 8,
                  search_dtype: Optional[str] = None, autotune: bool = True,
                  restarts: int = 1, chalf_headroom_bits: int = 4,
-                 overflow_policy: str = "recalibrate", chalf_exec_min_log2: int = -1):
+                 overflow_policy: str = "recalibrate", chalf_exec_min_log2: int = -1,
+                 mult: str = "auto", autotune_cache: Optional[str] = None):
         lib = _lib.load()
         self._lib = lib
         self._handle = ctypes.c_void_p()
@@ -89,13 +90,16 @@ class Plan:
         opts.chalf_headroom_bits = int(chalf_headroom_bits)
         opts.overflow_policy = OVERFLOW_POLICY[overflow_policy]
         opts.chalf_exec_min_log2 = int(chalf_exec_min_log2)
+        opts.mult = {"auto": _lib.LF_MULT_AUTO, "4m": _lib.LF_MULT_4M, "3m": _lib.LF_MULT_3M}[mult.lower()]
+        cache = autotune_cache.encode() if autotune_cache else None
+        opts.autotune_cache = cache
         c, arr = _circuit_struct(circuit)
         openq = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         cb = np.ascontiguousarray(self.closed_bits)
         st = lib.lf_build_network(ctypes.byref(c), openq, len(self.open_qubits),
                                   cb.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), cb.size,
                                   ctypes.byref(opts), ctypes.byref(self._handle))
-        del arr, keep
+        del arr, keep, cache
         check(st, "lf_build_network")
         self.workspace = None
         self.dtype = dtype

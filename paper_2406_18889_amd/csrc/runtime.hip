@@ -105,6 +105,7 @@ struct lf_plan {
   int recalibrations = 0;            // automatic recalibrations since bind
   uint64_t generation = 0;           // bumped whenever recorded launches go stale
   float slice_ms = -1.0f;            // measured time of one slice's steps (batch lane balance)
+  std::string tune_path;             // autotune_cache of the options (empty: none)
   // graph cache
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -494,6 +495,8 @@ void lf_plan_opts_default(lf_plan_opts* o) {
   o->chalf_headroom_bits = 4;
   o->overflow_policy = LF_OVERFLOW_RECALIBRATE;
   o->chalf_exec_min_log2 = -1;
+  o->mult = LF_MULT_AUTO;
+  o->autotune_cache = nullptr;
 }
 
 const char* lf_last_error(void) { return g_err.c_str(); }
@@ -537,8 +540,20 @@ lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits
     }
     std::vector<int> openq(open_qubits, open_qubits + n_open);
     std::vector<uint64_t> cb(closed_bits, closed_bits + n_batch);
+    if (o.mult == LF_MULT_3M)
+      return fail(LF_INVALID_ARGUMENT, "mult: 3M complex products are not implemented (4M only)");
+    if (o.mult != LF_MULT_AUTO && o.mult != LF_MULT_4M) return fail(LF_INVALID_ARGUMENT, "mult");
     auto P = std::make_unique<lf_plan>();
     P->opts = o;
+    P->opts.autotune_cache = nullptr;   // the plan keeps its own copy of the path
+    if (o.autotune_cache) {
+      P->tune_path = o.autotune_cache;
+      if (FILE* f = std::fopen(o.autotune_cache, "r")) {
+        std::fclose(f);
+        lf_status r = lf_autotune_load(o.autotune_cache);
+        if (r) return r;
+      }
+    }
     std::string err = lf::build_network(circuit->n_qubits, gates, openq, cb, P->net);
     if (!err.empty()) return fail(LF_INVALID_ARGUMENT, err);
     lf::PlanOptions po;
@@ -813,6 +828,7 @@ static lf_status autotune(lf_plan* P, int64_t sigma, hipStream_t st) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (r == LF_OK) P->tuned = true;
+  if (r == LF_OK && !P->tune_path.empty()) r = lf_autotune_save(P->tune_path.c_str());
   return r;
 }
 

@@ -210,3 +210,28 @@ def test_bench_plan_matches_stored_slice_definition(lib):
         assert a not in used and b not in used and a != b
         used.update((a, b))
     assert len(pj["steps"]) == len(leaves) - 1
+
+
+def test_plan_options_mult_and_autotune_cache(lib, tmp_path):
+    """lf_plan_opts.mult: 4M (or AUTO) builds, 3M is rejected with a message
+    (the library computes every complex product as four real products);
+    autotune_cache: a missing file is not an error, an existing one is
+    merged into the process's kernel choices when the plan is built."""
+    import paper_2406_18889_amd as lf
+    from paper_2406_18889_amd import _lib
+    c = wl.random_circuit(3, 3, 4, seed=2)
+    o = [6, 7, 8]
+    cb = wl.closed_bitstrings(9, o, 4, seed=1)
+    for m in ("auto", "4m"):
+        lf.Plan(c, o, cb, mult=m).close()
+    with pytest.raises(_lib.LeapfrogError) as ex:
+        lf.Plan(c, o, cb, mult="3m")
+    assert "3M" in str(ex.value)
+    missing = str(tmp_path / "none.txt")
+    lf.Plan(c, o, cb, autotune_cache=missing).close()
+    path = tmp_path / "tune.txt"
+    path.write_text("3 9 4 5 1 1 1 11\n")
+    lf.Plan(c, o, cb, autotune_cache=str(path)).close()
+    out = tmp_path / "saved.txt"
+    lf.autotune_save(str(out))
+    assert "3 9 4 5 1 1 1 11" in out.read_text()
