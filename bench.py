@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--launch", default="stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=45.0)
+    ap.add_argument("--keep-batch-order", action="store_true",
+                    help="paper53: contract the closed strings in the given order (no sort by gathered bits)")
     ap.add_argument("--dump-steps", default="", help="write per-step shapes and times (json)")
     ap.add_argument("--autotune-cache", default=None,
                     help="kernel choices to load (default: the committed MI355X choices)")
@@ -342,7 +344,7 @@ def run_paper(args):
     closed = wl.closed_bitstrings(circ.n_qubits, openq, PAPER_STRINGS, seed=wl.BITSTRING_SEED)
     say(f"{closed.size} closed strings drawn")
     plan = lf.Plan(circ, openq, closed, dtype=args.dtype, launch=args.launch, check_overflow=False,
-                   autotune=not args.no_autotune, **PAPER_PLAN)
+                   autotune=not args.no_autotune, keep_batch_order=args.keep_batch_order, **PAPER_PLAN)
     info = plan.info()
     say(f"plan: 2^{info['n_sliced_wires']} slices of {info['macs_per_slice']:.3e} multiply-adds, "
         f"workspace {info['workspace_bytes'] / 2**30:.1f} GiB, batch padded to 2^{info['n_batch_log2']}")
@@ -391,7 +393,8 @@ def run_paper(args):
            "config": {"workload": "paper53", "qubits": circ.n_qubits, "cycles": spec["cycles"],
                       "open_qubits": len(openq), "closed_strings": PAPER_STRINGS,
                       "amplitudes_per_slice": n_amp, "max_log2_intermediate": info["max_log2_intermediate"],
-                      "slices_total_log2": info["n_sliced_wires"]},
+                      "slices_total_log2": info["n_sliced_wires"],
+                      "batch_order": "given" if args.keep_batch_order else "sorted by gathered bits"},
            "macs_per_slice": info["macs_per_slice"],
            "algorithmic_tflops": value * flops / 1e12,
            "mfma_frac_algorithmic": value * flops / 1e12 /

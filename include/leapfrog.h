@@ -128,6 +128,12 @@ typedef struct lf_plan_opts {
                                     format): merged into the process's choices when the
                                     plan is built (if the file exists) and rewritten with
                                     them after the plan's first contraction has tuned */
+  int32_t keep_batch_order;      /* 0 (default): the library contracts the closed strings
+                                    in its own order, sorted by the closed bits that select
+                                    the blocks of gathered operands (strings that share a
+                                    block become neighbours, so its reads hit in cache);
+                                    out_amps rows stay in the caller's order.  1: contract
+                                    them in the given order */
 } lf_plan_opts;
 
 typedef struct lf_plan_info {
@@ -200,6 +206,18 @@ lf_status lf_plan_steps(const lf_plan* plan, int32_t* dims, double* macs, double
 lf_status lf_plan_step_strides(const lf_plan* plan, int32_t step, int64_t* out);
 
 /*
+ * Operands of a batched step (Methods C, sparse final stem stages): for
+ * operand A (w = 0) and B (w = 1), info[3w] = 1 if the operand is stored per
+ * batch entry (the running batched tensor), 0 if it is a plain tensor whose
+ * block for closed string b is chosen by the bits of b at its closed qubits,
+ * -1 if the step is not batched; info[3w + 1] = the number of those qubits
+ * (at most 64), written to qa / qb (either may be NULL) with their element
+ * strides in sa / sb (either may be NULL).  info must hold 6 values.
+ */
+lf_status lf_plan_step_gather(const lf_plan* plan, int32_t step, int32_t* info, int32_t* qa, int64_t* sa,
+                              int32_t* qb, int64_t* sb);
+
+/*
  * Binds `bytes` of device memory at `dev_ptr` (256-byte aligned, owned by
  * the caller, at least info.workspace_bytes) and uploads the leaf tensors on
  * `stream`.  The workspace must stay valid until the plan is destroyed or
@@ -209,8 +227,8 @@ lf_status lf_plan_bind_workspace(lf_plan* plan, void* dev_ptr, uint64_t bytes, v
 
 /*
  * Contracts slices [slice_begin, slice_end) and ADDS their sum to
- * out_amps (device, complex128, [n_batch][2^l], (re, im) interleaved), in
- * float64, one slice after another in increasing order (deterministic).
+ * out_amps (device, complex128, [n_batch][2^l], (re, im) interleaved,
+ * 16-byte aligned, else LF_INVALID_ARGUMENT), in float64, one slice after another in increasing order (deterministic).
  * The full range gives the exact amplitudes; a prefix gives the fraction f
  * of Methods A.  begin == end is a no-op.  A plan is used by one stream at a
  * time.

@@ -57,7 +57,7 @@ class lf_plan_opts(ctypes.Structure):
                 ("autotune", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("chalf_headroom_bits", ctypes.c_int32), ("overflow_policy", ctypes.c_int32),
                 ("chalf_exec_min_log2", ctypes.c_int32), ("mult", ctypes.c_int32),
-                ("autotune_cache", ctypes.c_char_p)]
+                ("autotune_cache", ctypes.c_char_p), ("keep_batch_order", ctypes.c_int32)]
 
 
 class lf_overflow_info(ctypes.Structure):
@@ -102,6 +102,9 @@ SIGNATURES = {
     "lf_plan_steps": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "lf_plan_step_strides": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "lf_plan_step_gather": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
     "lf_plan_bind_workspace": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P]),
     "lf_contract_slices": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "lf_plan_overflow": (ctypes.c_int32, [_P, _P, ctypes.POINTER(lf_overflow_info), ctypes.c_int32]),

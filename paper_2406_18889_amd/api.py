@@ -57,7 +57,8 @@ class Plan:
                  search_dtype: Optional[str] = None, autotune: bool = True,
                  restarts: int = 1, chalf_headroom_bits: int = 4,
                  overflow_policy: str = "recalibrate", chalf_exec_min_log2: int = -1,
-                 mult: str = "auto", autotune_cache: Optional[str] = None):
+                 mult: str = "auto", autotune_cache: Optional[str] = None,
+                 keep_batch_order: bool = False):
         lib = _lib.load()
         self._lib = lib
         self._handle = ctypes.c_void_p()
@@ -93,6 +94,7 @@ class Plan:
         opts.mult = {"auto": _lib.LF_MULT_AUTO, "4m": _lib.LF_MULT_4M, "3m": _lib.LF_MULT_3M}[mult.lower()]
         cache = autotune_cache.encode() if autotune_cache else None
         opts.autotune_cache = cache
+        opts.keep_batch_order = int(bool(keep_batch_order))
         c, arr = _circuit_struct(circuit)
         openq = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         cb = np.ascontiguousarray(self.closed_bits)
@@ -147,6 +149,21 @@ class Plan:
                                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
               "lf_plan_step_strides")
         return out[:n]
+
+    def step_gather(self, step: int):
+        """Operands of a batched step: [(stored_batched, qubits, strides)] for
+        A and B (stored_batched -1 when the step is not batched)."""
+        info = np.zeros(6, np.int32)
+        q = [np.zeros(64, np.int32), np.zeros(64, np.int32)]
+        s = [np.zeros(64, np.int64), np.zeros(64, np.int64)]
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        i64 = ctypes.POINTER(ctypes.c_int64)
+        check(self._lib.lf_plan_step_gather(self._handle, step, info.ctypes.data_as(i32),
+                                            q[0].ctypes.data_as(i32), s[0].ctypes.data_as(i64),
+                                            q[1].ctypes.data_as(i32), s[1].ctypes.data_as(i64)),
+              "lf_plan_step_gather")
+        return [(int(info[3 * w]), q[w][:info[3 * w + 1]].tolist(), s[w][:info[3 * w + 1]].tolist())
+                for w in range(2)]
 
     # ------------------------------------------------------------- device
     def bind(self, workspace=None, stream=None):

@@ -85,13 +85,16 @@ struct SliceCopy {
 hipError_t launch_instantiate(const SliceCopy* tab, int n_entries, int64_t max_n, char* ws,
                               const int64_t* sigma_dev, int64_t sigma, hipStream_t s);
 
-// out[i] += root[i] * scale for i < n (complex128 accumulator, float64 math),
-// unless *sat is nonzero (a complex-half value of this slice or an earlier
-// one saturated): then nothing is added and *first_bad = min(*first_bad,
-// slice number), the slice number read from *sigma_dev when it is not null.
-hipError_t launch_accumulate(int root_dt, const void* root, double* out, int64_t n, double scale,
-                             const unsigned* sat, unsigned long long* first_bad,
-                             const int64_t* sigma_dev, int64_t sigma, hipStream_t s);
+// out[d(i)] += root[i] * scale for i < n (complex128 accumulator, float64
+// math), where root rows hold 2^lbits values and d maps row z to row
+// rows[z] (d(i) = i when rows is null), unless *sat is nonzero (a
+// complex-half value of this slice or an earlier one saturated): then
+// nothing is added and *first_bad = min(*first_bad, slice number), the slice
+// number read from *sigma_dev when it is not null.
+hipError_t launch_accumulate(int root_dt, const void* root, double* out, int64_t n, int lbits,
+                             const int64_t* rows, double scale, const unsigned* sat,
+                             unsigned long long* first_bad, const int64_t* sigma_dev, int64_t sigma,
+                             hipStream_t s);
 
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);

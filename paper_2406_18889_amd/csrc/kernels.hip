@@ -1239,122 +1239,272 @@ __global__ void __launch_bounds__(64 * NW, STAGES == 2 ? 2 : 1) gett_mfma_dma(Ge
 }
 
 // ------------------------------------------------------------ skinny MFMA
-// Steps with a short side: N <= 16 complex (at most 32 rows of B'),
-// 4 <= K <= 64, complex-half A, M >= 32 GPW.  Each wave multiplies 32 rows of
-// A at a time by the whole of B', which it holds in registers (built once per
-// wave), with MFMA 32x32x16 and no LDS.  A is streamed from HBM once and C
-// written once, so the step is bound by HBM rather than by the vector ALU
-// rate of the one-row-per-thread kernels.  A complex64 B is split into a
-// high and a low half (two MFMAs per k step), which keeps its rounding at
-// about 2^-22 relative.  A wave takes GPW consecutive 32-row groups, all
-// inside one batch entry z, and issues all of their loads before its MFMAs.
-template <typename TB, typename TO, int KC, int GPW>
+// Steps with a short side: N <= 32 complex (NF = 1 or 2 fragments of 32 B'
+// rows), 4 <= K <= 64, complex-half A, M >= 32 GPW.  Each wave multiplies 32
+// rows of A at a time by the whole of B', which it holds in registers, with
+// MFMA 32x32x16 and no LDS.  A is streamed from HBM once and C written once,
+// so the step is bound by HBM rather than by the vector ALU rate of the
+// one-row-per-thread kernels; with M = 32 (GPW = 1) it is the batched
+// 32 x 32 products of the last stem steps, one wave per batch entry instead
+// of a mostly empty tile per entry.  A complex64 B is split into a high and
+// a low half (two MFMAs per k step), which keeps its rounding at about 2^-22
+// relative.  A wave takes GPW consecutive 32-row groups (its slab of m) of
+// ZC consecutive batch entries z, one entry after another: it reloads the A
+// (B) fragments only when the gathered block of A (B) changes from one entry
+// to the next, so in a batch sorted by the closed bits of a gathered operand
+// each of its blocks is read once per run of entries that share it instead
+// of once per entry.
+template <typename TB, typename TO, int KC, int GPW, int NF = 1, int ZC = 1, int NSB = 0>
 __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) {
   constexpr int S = KC >= 8 ? KC / 8 : 1;   // k steps of 16 reals
   constexpr bool SPLIT = std::is_same<TB, float>::value;
-  __shared__ int64_t cnT[16];
+  constexpr int BW = SPLIT ? 2 : 1;          // raw 16-byte words of B per (fragment, k step)
+  static_assert(NF == 1 || (NF == 2 && !SPLIT), "two B' fragments: complex-half B only");
+  static_assert(ZC >= 1 && ZC <= 64, "entries per wave: one lane each for their offsets");
+  static_assert(NSB == 0 || (!SPLIT && NF == 1 && NSB <= 16), "staged B: complex-half, one fragment");
+  constexpr int RW = KC >= 4 ? KC / 4 + 1 : 2;   // 16-byte words per staged B row (one of padding)
+  __shared__ int64_t cnT[16 * NF];
+  __shared__ uint4 sB[NSB > 0 ? ZC * NSB * RW : 1];
   const int64_t M = int64_t(1) << a.nm;
+  const int64_t Z = int64_t(1) << a.nz;
   const int N = 1 << a.nn;
   const int lane = threadIdx.x & 63;
   if (threadIdx.x < N) cnT[threadIdx.x] = scatter_bits(threadIdx.x, a.cn, a.nn);
-  __syncthreads();
-  const int64_t wave = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (wave >= n_waves) return;
-  const int64_t row0 = wave * (32 * GPW);          // first row (z, m) of this wave
-  const int64_t z = row0 >> a.nm;
-  const int64_t m0 = row0 & (M - 1);
-  const int kq = 4 * (lane >> 5);                  // complex k offset of this lane in a step
-
-  // B' fragments: lane row n' = lane % 32, n = n' / 2
-  const BPrime bp(lane & 1);
-  const int n = (lane & 31) >> 1;
-  const int64_t bz = a.offB ? a.offB[z] : z * int64_t(N) * KC;
-  f16x8 bh[S], bl[S];
-#pragma unroll
-  for (int st = 0; st < S; ++st) {
-    const int kc = st * 8 + kq;
-    uint4 hi = make_uint4(0, 0, 0, 0), lo = make_uint4(0, 0, 0, 0);
-    if (n < N && kc < KC) {
-      if constexpr (SPLIT) {
-        const float* p = static_cast<const float*>(a.B) + 2 * (bz + int64_t(n) * KC + kc);
-        const float4 v0 = reinterpret_cast<const float4*>(p)[0];
-        const float4 v1 = reinterpret_cast<const float4*>(p)[1];
-        const float x[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-        uint32_t wh[4], wl[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          f16x2 h, l;
-          h[0] = (_Float16)x[2 * e];
-          h[1] = (_Float16)x[2 * e + 1];
-          l[0] = (_Float16)(x[2 * e] - float(h[0]));
-          l[1] = (_Float16)(x[2 * e + 1] - float(h[1]));
-          __builtin_memcpy(&wh[e], &h, 4);
-          __builtin_memcpy(&wl[e], &l, 4);
-        }
-        hi = make_uint4(wh[0], wh[1], wh[2], wh[3]);
-        lo = make_uint4(wl[0], wl[1], wl[2], wl[3]);
-      } else {
-        hi = *reinterpret_cast<const uint4*>(static_cast<const _Float16*>(a.B) + 2 * (bz + int64_t(n) * KC + kc));
+  const int slab_bits = a.nm - (GPW == 1 ? 5 : GPW == 2 ? 6 : 7);   // slabs of 32 GPW rows per entry
+  if constexpr (NSB > 0) {
+    // the four waves of the block share one chunk of ZC entries (at least
+    // four slabs, checked at launch): their B blocks are read once, by all
+    // threads at a time, into LDS, rather than entry by entry by each wave
+    const int CPE = N * (KC / 4);                  // 16-byte words per entry
+    const int64_t zc0 = ((int64_t(blockIdx.x) * 4) >> slab_bits) * ZC;
+    for (int i = threadIdx.x; i < ZC * CPE; i += 256) {
+      const int e = i / CPE, w = i - e * CPE, n = w / (KC / 4), c4 = w - n * (KC / 4);
+      const int64_t z = zc0 + e;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (z < Z) {
+        const int64_t bz = a.offB ? a.offB[z] : z * int64_t(N) * KC;
+        v = *reinterpret_cast<const uint4*>(static_cast<const _Float16*>(a.B) + 2 * (bz + int64_t(n) * KC + 4 * c4));
       }
+      sB[(e * NSB + n) * RW + c4] = v;
     }
-    bh[st] = bprime_frag(hi, bp);
-    if constexpr (SPLIT) bl[st] = bprime_frag(lo, bp);
   }
-
-  const _Float16* A = static_cast<const _Float16*>(a.A) + 2 * (a.offA ? a.offA[z] : z * M * KC);
-  f16x8 af[GPW][S];
+  __syncthreads();
+  const int64_t wave = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wave >= n_waves) return;
+  const int64_t m0 = (wave & ((int64_t(1) << slab_bits) - 1)) * (32 * GPW);
+  const int64_t z0 = (wave >> slab_bits) * ZC;
+  const int kq = 4 * (lane >> 5);                  // complex k offset of this lane in a step
+  const BPrime bp(lane & 1);                       // B' row n' = lane % 32 of fragment f: n = 16 f + n' / 2
+  const _Float16* Abase = static_cast<const _Float16*>(a.A);
+  TO* C = static_cast<TO*>(a.C);
+  // the operand offsets of the wave's entries, lane i holding those of entry
+  // z0 + i, read once (a gather table lookup per entry would put one memory
+  // latency between consecutive entries)
+  const int64_t zl = z0 + (lane < ZC ? lane : 0);
+  const int64_t myA = zl < Z ? (a.offA ? a.offA[zl] : zl * M * KC) : 0;
+  const int64_t myB = zl < Z ? (a.offB ? a.offB[zl] : zl * int64_t(N) * KC) : 0;
+  auto lane64 = [](int64_t v, int i) {
+    return int64_t((uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint64_t(v) >> 32), i))) << 32) |
+                   uint32_t(__builtin_amdgcn_readlane(int(v), i)));
+  };
+  auto offA = [&](int64_t z) { return lane64(myA, int(z - z0)); };
+  auto offB = [&](int64_t z) { return lane64(myB, int(z - z0)); };
+  // raw B words of an entry (complex-half: 8 halves; complex64: 8 floats in two words)
+  auto load_b = [&](int64_t bz, uint4 (&rb)[NF][S][BW]) __attribute__((always_inline)) {
 #pragma unroll
-  for (int g = 0; g < GPW; ++g)
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int st = 0; st < S; ++st) {
+        const int n = 16 * f + ((lane & 31) >> 1);
+        const int kc = st * 8 + kq;
+#pragma unroll
+        for (int w = 0; w < BW; ++w) rb[f][st][w] = make_uint4(0, 0, 0, 0);
+        if (n < N && kc < KC) {
+          if constexpr (SPLIT) {
+            const uint4* p = reinterpret_cast<const uint4*>(static_cast<const float*>(a.B) + 2 * (bz + int64_t(n) * KC + kc));
+            rb[f][st][0] = p[0];
+            rb[f][st][BW - 1] = p[1];
+          } else {
+            rb[f][st][0] = *reinterpret_cast<const uint4*>(static_cast<const _Float16*>(a.B) +
+                                                           2 * (bz + int64_t(n) * KC + kc));
+          }
+        }
+      }
+  };
+  // the same from the staged copy (entry e of the chunk)
+  auto load_b_lds = [&](int e, uint4 (&rb)[NF][S][BW]) __attribute__((always_inline)) {
 #pragma unroll
     for (int st = 0; st < S; ++st) {
+      const int n = (lane & 31) >> 1;
       const int kc = st * 8 + kq;
-      const int64_t m = m0 + g * 32 + (lane & 31);
-      if (kc < KC) {
-        af[g][st] = *reinterpret_cast<const f16x8*>(A + 2 * (m * KC + kc));
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) af[g][st][e] = (_Float16)0.0f;
-      }
+      rb[0][st][0] = (n < N && kc < KC) ? sB[(e * NSB + n) * RW + kc / 4] : make_uint4(0, 0, 0, 0);
     }
-
-  TO* C = static_cast<TO*>(a.C);
-  const int64_t czv = scatter_bits(z, a.cz, a.nz);
+  };
+  auto load_a = [&](int64_t az, f16x8 (&af)[GPW][S]) __attribute__((always_inline)) {
+    const _Float16* A = Abase + 2 * az;
+#pragma unroll
+    for (int g = 0; g < GPW; ++g)
+#pragma unroll
+      for (int st = 0; st < S; ++st) {
+        const int kc = st * 8 + kq;
+        const int64_t m = m0 + g * 32 + (lane & 31);
+        if (kc < KC) {
+          af[g][st] = *reinterpret_cast<const f16x8*>(A + 2 * (m * KC + kc));
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) af[g][st][e] = (_Float16)0.0f;
+        }
+      }
+  };
+  // B' fragments from the raw words (complex64: rounded high part and the
+  // rounded remainder)
+  f16x8 bh[NF][S], bl[S];
+  auto form_b = [&](const uint4 (&rb)[NF][S][BW]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int st = 0; st < S; ++st) {
+        if constexpr (SPLIT) {
+          float x[8];
+          __builtin_memcpy(x, &rb[f][st][0], 16);
+          __builtin_memcpy(x + 4, &rb[f][st][BW - 1], 16);
+          uint32_t wh[4], wl[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            f16x2 h, l;
+            h[0] = (_Float16)x[2 * e];
+            h[1] = (_Float16)x[2 * e + 1];
+            l[0] = (_Float16)(x[2 * e] - float(h[0]));
+            l[1] = (_Float16)(x[2 * e + 1] - float(h[1]));
+            __builtin_memcpy(&wh[e], &h, 4);
+            __builtin_memcpy(&wl[e], &l, 4);
+          }
+          bh[f][st] = bprime_frag(make_uint4(wh[0], wh[1], wh[2], wh[3]), bp);
+          bl[st] = bprime_frag(make_uint4(wl[0], wl[1], wl[2], wl[3]), bp);
+        } else {
+          bh[f][st] = bprime_frag(rb[f][st][0], bp);
+        }
+      }
+  };
+  // One entry after another; the next entry's B words (and, for one-group
+  // waves, its A fragments when its block differs) are requested before this
+  // entry's MFMAs, so their latency overlaps the arithmetic and the stores.
+  // Waves of several groups reload A in place, only where the block changes.
+  constexpr bool PIPE_A = GPW == 1;
+  uint4 rb[NF][S][BW];
+  f16x8 af[GPW][S], an[GPW][S];
   float lmax = 0.0f;
   unsigned lsat = 0;
+  if (z0 < Z) {
+    int64_t curB = offB(z0), curA = offA(z0);
+    if constexpr (NSB > 0) load_b_lds(0, rb);
+    else load_b(curB, rb);
+    load_a(curA, af);
+    for (int zi = 0; zi < ZC; ++zi) {
+      const int64_t z = z0 + zi;
+      if (z >= Z) break;
+      form_b(rb);
+      const bool more = zi + 1 < ZC && z + 1 < Z;
+      const int64_t nB = more ? offB(z + 1) : curB;
+      const int64_t nA = more ? offA(z + 1) : curA;
+      if (nB != curB) {
+        if constexpr (NSB > 0) load_b_lds(zi + 1, rb);
+        else load_b(nB, rb);
+      }
+      if constexpr (PIPE_A) {
+        if (nA != curA) load_a(nA, an);
+      }
+      const int64_t czv = scatter_bits(z, a.cz, a.nz);
 #pragma unroll
-  for (int g = 0; g < GPW; ++g) {
-    f32x16 acc;
+      for (int g = 0; g < GPW; ++g) {
+        f32x16 acc[NF];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
-    for (int st = 0; st < S; ++st) {
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[st], af[g][st], acc, 0, 0, 0);
-      if constexpr (SPLIT) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[st], af[g][st], acc, 0, 0, 0);
-    }
-    const int64_t m = m0 + g * 32 + (lane & 31);
-    const int64_t cb = czv + scatter_bits(m, a.cm, a.nm);
+          for (int v = 0; v < 16; ++v) acc[f][v] = 0.0f;
 #pragma unroll
-    for (int v = 0; v < 16; v += 2) {
-      const int nl = (8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1;
-      if (nl >= N) continue;
-      const float re = acc[v] * a.scale, im = acc[v + 1] * a.scale;
-      lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
-      if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
+        for (int st = 0; st < S; ++st)
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            acc[f] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[f][st], af[g][st], acc[f], 0, 0, 0);
+            if constexpr (SPLIT) acc[f] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[st], af[g][st], acc[f], 0, 0, 0);
+          }
+        const int64_t m = m0 + g * 32 + (lane & 31);
+        const int64_t cb = czv + scatter_bits(m, a.cm, a.nm);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int v = 0; v < 16; v += 2) {
+            const int nl = 16 * f + ((8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1);
+            if (nl >= N) continue;
+            const float re = acc[f][v] * a.scale, im = acc[f][v + 1] * a.scale;
+            lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+            if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
+          }
+      }
+      if (nA != curA) {
+        if constexpr (PIPE_A) {
+#pragma unroll
+          for (int g = 0; g < GPW; ++g)
+#pragma unroll
+            for (int st = 0; st < S; ++st) af[g][st] = an[g][st];
+        } else {
+          load_a(nA, af);
+        }
+      }
+      curA = nA;
+      curB = nB;
     }
   }
   block_amax_sat(lmax, lsat, a.amax, a.sat);
 }
 
+// waves: (2^nz / ZC) entry chunks x (M / 32 GPW) slabs; ZC = 16 consecutive
+// entries per wave for batched steps with at least 2^8 entries, else one
+template <typename TB, typename TO, int KC, int GPW, int NF>
+static hipError_t launch_skinny_g(const GettArgs& a, hipStream_t s) {
+  if (((int64_t(1) << a.nm) % (32 * GPW)) != 0) return hipErrorInvalidValue;
+  const int64_t slabs = (int64_t(1) << a.nm) / (32 * GPW);
+  if (a.nz >= 8) {
+    const int64_t n_waves = ((int64_t(1) << a.nz) / 16) * slabs;
+    const int64_t blocks = (n_waves + 3) / 4;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    // B staged in LDS per chunk when every block's four waves share a chunk
+    if constexpr (!std::is_same<TB, float>::value && NF == 1) {
+      if (slabs % 4 == 0 && a.nn <= 3) {
+        hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 16, 8>), dim3(unsigned(blocks)), dim3(256), 0, s, a,
+                           n_waves);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 16>), dim3(unsigned(blocks)), dim3(256), 0, s, a, n_waves);
+  } else {
+    const int64_t n_waves = (int64_t(1) << a.nz) * slabs;
+    const int64_t blocks = (n_waves + 3) / 4;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 1>), dim3(unsigned(blocks)), dim3(256), 0, s, a, n_waves);
+  }
+  return hipGetLastError();
+}
+
+// GPW: 32-row groups per wave (fewer when M is smaller); NF = 2 for N > 16
 template <typename TB, typename TO, int KC>
 static hipError_t launch_skinny_k(const GettArgs& a, hipStream_t s) {
-  constexpr int GPW = KC >= 64 ? 2 : 4;
-  const int64_t rows = (int64_t(1) << a.nz) << a.nm;
-  if (((int64_t(1) << a.nm) % (32 * GPW)) != 0) return hipErrorInvalidValue;
-  const int64_t n_waves = rows / (32 * GPW);
-  const int64_t blocks = (n_waves + 3) / 4;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW>), dim3(unsigned(blocks)), dim3(256), 0, s, a, n_waves);
-  return hipGetLastError();
+  constexpr int G = KC >= 64 ? 2 : 4;
+  if (a.nn > 5 || a.nm < 5) return hipErrorInvalidValue;
+  if (a.nn == 5) {
+    if constexpr (std::is_same<TB, float>::value) {
+      return hipErrorInvalidValue;
+    } else {
+      if constexpr (KC < 64) {
+        if (a.nm >= 6) return launch_skinny_g<TB, TO, KC, 2, 2>(a, s);
+      }
+      return launch_skinny_g<TB, TO, KC, 1, 2>(a, s);
+    }
+  }
+  if ((int64_t(1) << a.nm) >= 32 * G) return launch_skinny_g<TB, TO, KC, G, 1>(a, s);
+  if (a.nm >= 6) return launch_skinny_g<TB, TO, KC, 2, 1>(a, s);
+  return launch_skinny_g<TB, TO, KC, 1, 1>(a, s);
 }
 
 template <typename TB, typename TO>
@@ -1485,7 +1635,7 @@ bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
   if (kernel == K_MFMA_WIDE) return in_dt == 1 && nm >= 7 && nn >= 6;
   if (kernel == K_MFMA_DB || kernel == K_MFMA_DEEP) return in_dt == 1 && nm >= 7 && nn >= 6;
   if (kernel == K_NARROW) return nm >= 8 && nk <= 6 && nn <= 8 && nn + nk <= 8;
-  if (kernel == K_SKINNY) return in_dt == 1 && nn <= 4 && nk >= 2 && nk <= 6 && nm >= (nk == 6 ? 6 : 7);
+  if (kernel == K_SKINNY) return in_dt == 1 && nn <= 5 && nk >= 2 && nk <= 6 && nm >= 5;
   // whole 256 x 128 tiles, K a multiple of 32, and per-lane load offsets
   // (row * K * 4 bytes within a 256-row panel) that fit 32 bits
   if (kernel == K_MFMA_DMA || kernel == K_MFMA_DMA_X || kernel == K_MFMA_DMA4 || kernel == K_MFMA_DMA4_X)
@@ -1571,7 +1721,7 @@ hipError_t launch_gett(int kernel, int a_dt, int b_dt, int out_dt, const GettArg
     if (a_dt != 1 || b_dt != 0) return hipErrorInvalidValue;
     if (kernel == K_NARROW && kernel_applicable(K_NARROW, 1, a.nz, a.nm, a.nn, a.nk))
       return out_dt ? launch_narrow<_Float16, float, _Float16>(a, s) : launch_narrow<_Float16, float, float>(a, s);
-    if (kernel == K_SKINNY && kernel_applicable(K_SKINNY, 1, a.nz, a.nm, a.nn, a.nk))
+    if (kernel == K_SKINNY && a.nn <= 4 && kernel_applicable(K_SKINNY, 1, a.nz, a.nm, a.nn, a.nk))
       return out_dt ? launch_skinny<float, _Float16>(a, s) : launch_skinny<float, float>(a, s);
     return out_dt ? launch_thin<_Float16, float, _Float16>(a, s) : launch_thin<_Float16, float, float>(a, s);
   }
@@ -1618,10 +1768,14 @@ hipError_t launch_instantiate(const SliceCopy* tab, int n_entries, int64_t max_n
 // an earlier one) was clamped.  The slice is then left out and the smallest
 // such slice number is recorded, so the accumulator holds exactly the slices
 // before the first saturated one.
+// Each block takes chunks of 1024 values, a thread four of them 256 apart
+// (every load and store instruction of a wave covers one contiguous piece:
+// 256 B of the root, 1 KB of the accumulator as 16-byte complex128), with
+// all four root loads issued before the read-modify-writes.
 template <typename T>
-__global__ void __launch_bounds__(256) accumulate_kernel(const T* root, double* out, int64_t n,
-                                                         double scale, const unsigned* sat,
-                                                         unsigned long long* first_bad,
+__global__ void __launch_bounds__(256) accumulate_kernel(const T* root, double* out, int64_t n, int lbits,
+                                                         const int64_t* rows, double scale,
+                                                         const unsigned* sat, unsigned long long* first_bad,
                                                          const int64_t* sigma_dev, int64_t sigma) {
   if (sat && *sat) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1630,28 +1784,48 @@ __global__ void __launch_bounds__(256) accumulate_kernel(const T* root, double* 
     }
     return;
   }
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    float re, im;
-    CIO<T>::load(root, i, re, im);
-    out[2 * i] += double(re) * scale;
-    out[2 * i + 1] += double(im) * scale;
+  const int64_t mask = (int64_t(1) << lbits) - 1;
+  double2* o = reinterpret_cast<double2*>(out);
+  for (int64_t c = int64_t(blockIdx.x) * 1024; c < n; c += int64_t(gridDim.x) * 1024) {
+    float re[4], im[4];
+    int64_t d[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = c + v * 256 + threadIdx.x;
+      d[v] = -1;
+      re[v] = im[v] = 0.0f;
+      if (i < n) {
+        CIO<T>::load(root, i, re[v], im[v]);
+        d[v] = rows ? (rows[i >> lbits] << lbits) | (i & mask) : i;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (d[v] >= 0) {
+        double2 x = o[d[v]];
+        x.x += double(re[v]) * scale;
+        x.y += double(im[v]) * scale;
+        o[d[v]] = x;
+      }
   }
 }
 
-hipError_t launch_accumulate(int root_dt, const void* root, double* out, int64_t n, double scale,
-                             const unsigned* sat, unsigned long long* first_bad,
-                             const int64_t* sigma_dev, int64_t sigma, hipStream_t s) {
-  int64_t b = (n + 255) / 256;
-  if (b > 4096) b = 4096;
+hipError_t launch_accumulate(int root_dt, const void* root, double* out, int64_t n, int lbits,
+                             const int64_t* rows, double scale, const unsigned* sat,
+                             unsigned long long* first_bad, const int64_t* sigma_dev, int64_t sigma,
+                             hipStream_t s) {
+  if (lbits < 0 || lbits > 62) return hipErrorInvalidValue;
+  int64_t b = (n + 1023) / 1024;
+  if (b > 8192) b = 8192;
   if (b < 1) b = 1;
   if (root_dt == 0)
     hipLaunchKernelGGL(accumulate_kernel<float>, dim3(unsigned(b)), dim3(256), 0, s,
-                       static_cast<const float*>(root), out, n, scale, sat, first_bad, sigma_dev, sigma);
+                       static_cast<const float*>(root), out, n, lbits, rows, scale, sat, first_bad, sigma_dev,
+                       sigma);
   else
     hipLaunchKernelGGL(accumulate_kernel<_Float16>, dim3(unsigned(b)), dim3(256), 0, s,
-                       static_cast<const _Float16*>(root), out, n, scale, sat, first_bad, sigma_dev,
-                       sigma);
+                       static_cast<const _Float16*>(root), out, n, lbits, rows, scale, sat, first_bad,
+                       sigma_dev, sigma);
   return hipGetLastError();
 }
 

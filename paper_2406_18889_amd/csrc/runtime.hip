@@ -88,6 +88,11 @@ struct lf_plan {
   std::vector<int> shift;          // per step (complex-half results)
   std::vector<lf::SliceCopy> copies;
   std::vector<int64_t> gtab_off;   // per step: byte offset of [offA | offB] tables, -1 if none
+  // batch entry z (contraction order) -> the caller's closed string; empty
+  // when the two orders agree.  Its device copy (int64 per string) sits at
+  // off_rows and maps root rows to out_amps rows.
+  std::vector<int64_t> batch_src;
+  int64_t off_rows = -1;
   int64_t copy_max_n = 0;
   int64_t off_copies_tab = 0, off_sigma = 0, off_sat = 0, off_amax = 0;
   // off_sat holds the saturation counter (uint32) and, 8 bytes on, the first
@@ -167,6 +172,64 @@ lf_status clear_sat(lf_plan* P, hipStream_t st) {
 }
 
 // -------------------------------------------------------- memory planning
+// Contraction order of the closed strings.  A gathered operand of a batched
+// step has one block per value of its closed bits, so strings that agree on
+// those bits read the same block; sorted so that such strings are
+// neighbours, the reads of one block follow each other and hit in cache
+// instead of going to HBM once per string.  Sort key: the closed qubits of
+// the gathered operands, the operand with the most gathered elements per
+// slice first (slice-invariant steps last), within an operand by descending
+// stride, so that strings next to each other also read blocks next to each
+// other.  Padding entries (copies of string 0) stay at the end.
+void order_batch(lf_plan* P) {
+  Network& net = P->net;
+  const int64_t B = net.n_batch;
+  if (net.nb == 0 || B < 2) return;
+  struct Op {
+    double w;
+    std::vector<std::pair<int64_t, int>> q;   // (stride, qubit)
+  };
+  std::vector<Op> ops;
+  for (const StepLayout& st : P->hp.steps) {
+    if (!st.batched) continue;
+    auto add = [&](const Gather& g, int block_bits) {
+      if (g.stored_batched || g.q.empty()) return;
+      Op op;
+      op.w = std::ldexp(1.0, st.nz + block_bits) * (st.variant ? 1.0 : 1e-12);
+      for (size_t i = 0; i < g.q.size(); ++i) op.q.push_back({g.stride[i], g.q[i]});
+      std::stable_sort(op.q.begin(), op.q.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+      ops.push_back(std::move(op));
+    };
+    add(st.ga, st.nm + st.nk);
+    add(st.gb, st.nn + st.nk);
+  }
+  std::stable_sort(ops.begin(), ops.end(), [](const Op& x, const Op& y) { return x.w > y.w; });
+  std::vector<int> bits;
+  std::vector<char> used(64, 0);
+  for (const Op& op : ops)
+    for (const auto& sq : op.q)
+      if (sq.second >= 0 && sq.second < 64 && !used[size_t(sq.second)]) {
+        used[size_t(sq.second)] = 1;
+        bits.push_back(sq.second);
+      }
+  if (bits.empty()) return;
+  std::vector<uint64_t> key(size_t(B), 0);
+  for (int64_t b = 0; b < B; ++b) {
+    uint64_t k = 0;
+    for (int q : bits) k = (k << 1) | ((net.closed_padded[size_t(b)] >> q) & 1);
+    key[size_t(b)] = k;
+  }
+  std::vector<int64_t> perm(static_cast<size_t>(B));
+  for (int64_t b = 0; b < B; ++b) perm[size_t(b)] = b;
+  std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return key[size_t(x)] < key[size_t(y)]; });
+  bool identity = true;
+  for (int64_t z = 0; z < B && identity; ++z) identity = perm[size_t(z)] == z;
+  if (identity) return;
+  std::vector<uint64_t> given(net.closed_padded.begin(), net.closed_padded.begin() + B);
+  for (int64_t z = 0; z < B; ++z) net.closed_padded[size_t(z)] = given[size_t(perm[size_t(z)])];
+  P->batch_src = std::move(perm);
+}
+
 std::string plan_memory(lf_plan* P) {
   const HostPlan& hp = P->hp;
   const Network& net = P->net;
@@ -288,6 +351,10 @@ std::string plan_memory(lf_plan* P) {
     if (!hp.steps[s].batched) continue;
     P->gtab_off[s] = cur;
     cur += align_up(int64_t(2 * sizeof(int64_t)) << hp.steps[s].nz);
+  }
+  if (!P->batch_src.empty()) {
+    P->off_rows = cur;
+    cur += align_up(int64_t(sizeof(int64_t)) * int64_t(P->batch_src.size()));
   }
   // control block
   P->off_sigma = cur;
@@ -460,8 +527,10 @@ lf_status run_slice(lf_plan* P, const int64_t* sigma_dev, int64_t sigma, double*
     if (tk) HIPCHK(hipEventRecord(P->tev[2 * pair + 1], stream));
   }
   const int r = P->root;
-  const int64_t n = P->net.n_batch << P->net.open_qubits.size();
-  HIPCHK(launch_accumulate(P->store_dt[r], P->ws + P->off[r], out, n,
+  const int lbits = int(P->net.open_qubits.size());
+  const int64_t n = P->net.n_batch << lbits;
+  const int64_t* rows = P->off_rows >= 0 ? reinterpret_cast<const int64_t*>(P->ws + P->off_rows) : nullptr;
+  HIPCHK(launch_accumulate(P->store_dt[r], P->ws + P->off[r], out, n, lbits, rows,
                            std::ldexp(1.0, P->exp2[r]), sat_ptr(P), first_bad_ptr(P), sigma_dev,
                            sigma, stream));
   return LF_OK;
@@ -497,6 +566,7 @@ void lf_plan_opts_default(lf_plan_opts* o) {
   o->chalf_exec_min_log2 = -1;
   o->mult = LF_MULT_AUTO;
   o->autotune_cache = nullptr;
+  o->keep_batch_order = 0;
 }
 
 const char* lf_last_error(void) { return g_err.c_str(); }
@@ -604,6 +674,7 @@ lf_status lf_build_network(const lf_circuit* circuit, const int32_t* open_qubits
     for (auto& s : P->hp.steps)
       if (s.nz > lf::MAXZ || s.nm > lf::MAXMN || s.nn > lf::MAXMN)
         return fail(LF_PLAN_INFEASIBLE, "step rank exceeds kernel limits");
+    if (!o.keep_batch_order) order_batch(P.get());
     err = plan_memory(P.get());
     if (!err.empty()) return fail(LF_PLAN_INFEASIBLE, err);
     *out_plan = P.release();
@@ -688,6 +759,25 @@ lf_status lf_plan_step_strides(const lf_plan* P, int32_t step, int64_t* out) {
   return LF_OK;
 }
 
+lf_status lf_plan_step_gather(const lf_plan* P, int32_t step, int32_t* info, int32_t* qa, int64_t* sa,
+                              int32_t* qb, int64_t* sb) {
+  if (!P || !info || step < 0 || step >= int32_t(P->hp.steps.size())) return fail(LF_INVALID_ARGUMENT, "bad argument");
+  const lf::StepLayout& st = P->hp.steps[step];
+  auto one = [&](const lf::Gather& g, int32_t* inf, int32_t* q, int64_t* s) {
+    inf[0] = st.batched ? (g.stored_batched ? 1 : 0) : -1;
+    inf[1] = st.batched ? int32_t(g.q.size()) : 0;
+    inf[2] = 0;
+    for (int i = 0; i < inf[1]; ++i) {
+      if (q) q[i] = g.q[size_t(i)];
+      if (s) s[i] = g.stride[size_t(i)];
+    }
+  };
+  if (st.batched && (st.ga.q.size() > 64 || st.gb.q.size() > 64)) return fail(LF_INTERNAL, "gather wider than 64");
+  one(st.ga, info, qa, sa);
+  one(st.gb, info + 3, qb, sb);
+  return LF_OK;
+}
+
 lf_status lf_plan_bind_workspace(lf_plan* P, void* dev_ptr, uint64_t bytes, void* stream) {
   if (!P) return fail(LF_INVALID_ARGUMENT, "plan is NULL");
   if (!dev_ptr) return fail(LF_INVALID_ARGUMENT, "workspace is NULL");
@@ -759,6 +849,9 @@ lf_status lf_plan_bind_workspace(lf_plan* P, void* dev_ptr, uint64_t bytes, void
     HIPCHK(hipMemcpyAsync(P->ws + P->gtab_off[s], tabs.back().data(), 2 * Z * sizeof(int64_t),
                           hipMemcpyHostToDevice, st));
   }
+  if (P->off_rows >= 0)
+    HIPCHK(hipMemcpyAsync(P->ws + P->off_rows, P->batch_src.data(), P->batch_src.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice, st));
   if (!P->copies.empty())
     HIPCHK(hipMemcpyAsync(P->ws + P->off_copies_tab, P->copies.data(),
                           P->copies.size() * sizeof(lf::SliceCopy), hipMemcpyHostToDevice, st));
@@ -899,6 +992,7 @@ lf_status lf_contract_slices(lf_plan* P, int64_t s0, int64_t s1, void* out_amps,
   if (s0 < 0 || s1 < s0 || s1 > ns) return fail(LF_INVALID_ARGUMENT, "slice range outside [0, n_slices]");
   if (s0 == s1) return LF_OK;
   if (!out_amps) return fail(LF_INVALID_ARGUMENT, "out_amps is NULL");
+  if (reinterpret_cast<uintptr_t>(out_amps) % 16) return fail(LF_INVALID_ARGUMENT, "out_amps not 16-byte aligned");
   hipStream_t st = as_stream(stream);
   double* out = static_cast<double*>(out_amps);
   lf_status r = ensure_ready(P, s0, st);
@@ -1214,6 +1308,8 @@ lf_status lf_contract_batch(const lf_batch_item* items, int32_t n, int32_t mode,
       return fail(LF_INVALID_ARGUMENT, "item slice range outside [0, n_slices]");
     if (!items[i].out_amps && items[i].slice_end > items[i].slice_begin)
       return fail(LF_INVALID_ARGUMENT, "item out_amps is NULL");
+    if (reinterpret_cast<uintptr_t>(items[i].out_amps) % 16)
+      return fail(LF_INVALID_ARGUMENT, "item out_amps not 16-byte aligned");
     lf_status r = ensure_ready(P, items[i].slice_begin, st);
     if (r) return r;
   }

@@ -235,3 +235,41 @@ def test_plan_options_mult_and_autotune_cache(lib, tmp_path):
     out = tmp_path / "saved.txt"
     lf.autotune_save(str(out))
     assert "3 9 4 5 1 1 1 11" in out.read_text()
+
+
+def test_batched_step_gathers_cover_closed_qubits(lib):
+    """Every closed output leg is absorbed exactly once: over the batched
+    steps, the closed qubits of the gathered (plain) operands are disjoint
+    and together are all the closed qubits; the step where the batch index
+    appears gathers both operands, later ones read the running batched
+    tensor as one of them.  The batch order option changes no step."""
+    import paper_2406_18889_amd as lf
+    c = wl.random_circuit(4, 5, 10, seed=3)
+    o = [16, 17, 18, 19]
+    cb = wl.closed_bitstrings(20, o, 1000, seed=4)
+    for keep in (False, True):
+        p = lf.Plan(c, o, cb, max_log2=20, keep_batch_order=keep)
+        dims, _, _ = p.steps()
+        seen = []
+        first = None
+        for s in range(len(dims)):
+            g = p.step_gather(s)
+            if g[0][0] < 0:
+                assert g[1][0] < 0
+                continue
+            if first is None:
+                first = s
+                assert g[0][0] == 0 and g[1][0] == 0
+            else:
+                assert g[0][0] + g[1][0] >= 1
+            for stored, qs, strides in g:
+                if stored == 0:
+                    seen += qs
+                    assert all(st > 0 for st in strides)
+        closed = sorted(set(range(20)) - set(o))
+        assert first is not None
+        assert sorted(seen) == closed
+        if keep:
+            assert np.array_equal(dims, dims_sorted)
+        dims_sorted = dims
+        p.close()

@@ -97,6 +97,12 @@ SHAPES = [
     (8, 5, 5, 9), (3, 4, 3, 10), (0, 5, 5, 7), (2, 2, 5, 8),
     # the 128 x 128 two-stage tile: one m tile, one and two k tiles
     (1, 7, 7, 5), (2, 7, 8, 6),
+    # batched products with 32 or 64 rows per entry and N up to 32 complex
+    # (the last stem steps): one wave per 32 rows, one or two B' fragments
+    (3, 5, 5, 5), (2, 6, 5, 3), (1, 5, 5, 6), (2, 5, 3, 4), (4, 5, 5, 2), (1, 6, 4, 6),
+    # batched steps of at least 2^8 entries: 16 entries per wave; B staged in
+    # LDS per chunk when four slabs share it
+    (8, 5, 5, 5), (8, 8, 2, 6), (8, 9, 3, 3), (9, 6, 4, 4), (8, 7, 1, 2),
 ]
 
 
@@ -111,7 +117,7 @@ def _applicable(kernel, dt, shape):
     if kernel in (4, 5, 6, 9, 10):
         return dt == "chalf" and nm >= 7 and nn >= 6
     if kernel == 7:
-        return dt == "chalf" and nn <= 4 and 2 <= nk <= 6 and nm >= (6 if nk == 6 else 7)
+        return dt == "chalf" and nn <= 5 and 2 <= nk <= 6 and nm >= 5
     if kernel in (11, 12, 13, 14):
         return dt == "chalf" and nm >= 8 and nn >= 7 and 5 <= nk <= 21
     if kernel == 15:
@@ -240,7 +246,8 @@ def test_pair_chalf_streaming_layouts(lf, kernel, layout, shape):
 
 @pytest.mark.parametrize("kernel", [0, 3, 7])
 @pytest.mark.parametrize("shape", [(0, 10, 2, 2), (1, 9, 3, 3), (0, 10, 4, 4), (2, 7, 4, 5),
-                                   (0, 6, 3, 6), (0, 8, 0, 6), (0, 13, 2, 2)])
+                                   (0, 6, 3, 6), (0, 8, 0, 6), (0, 13, 2, 2), (3, 5, 3, 4),
+                                   (1, 5, 4, 6), (2, 6, 2, 3)])
 def test_pair_mixed_half_a_c64_b(lf, kernel, shape):
     """Complex-half A with a complex64 B (the planner keeps small B
     operands in complex64), complex64 result: B enters the streaming kernels
@@ -496,6 +503,69 @@ def test_rqc30_full_sum_complex_half(lf):
 
 
 # ------------------------------------------------- batched uneven subtasks
+@pytest.mark.parametrize("dtype", ["c64", "chalf"])
+def test_batch_order_does_not_change_amplitudes(lf, dtype):
+    """1000 closed strings (padded to 2^10) of a 20-qubit circuit: the
+    library's own contraction order (sorted by the gathered closed bits) and
+    the caller's order give the same out_amps bit for bit (each string's
+    values go through the same arithmetic), in the caller's row order, and
+    both match the state vector."""
+    _say(f"batch order {dtype}")
+    c = wl.random_circuit(4, 5, 10, seed=3)
+    o = [16, 17, 18, 19]
+    cb = wl.closed_bitstrings(20, o, 1000, seed=4)
+    ref = sv.group_amplitudes(c, o, cb)
+    outs = []
+    for keep in (False, True):
+        plan = lf.Plan(c, o, cb, dtype=dtype, max_log2=20, keep_batch_order=keep,
+                       chalf_min_log2=8).bind()
+        out = plan.contract(0, plan.info()["n_slices"])
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+        plan.workspace = None
+        plan.close()
+    assert outs[0].shape == (1000, 16)
+    assert np.array_equal(outs[0], outs[1])
+    assert rel_err(outs[0], ref) < (C64_TOL if dtype == "c64" else CHALF_TOL)
+
+
+def test_batched_skinny_steps_with_gathers(lf, tmp_path):
+    """The skinny kernel on the batched steps of a plan (entry chunks that
+    reuse a gathered block while it does not change, in the library's sorted
+    order and in the caller's order): kernel 7 is forced on every batched
+    step it applies to, and the amplitudes match the state vector."""
+    _say("batched skinny steps")
+    c = wl.random_circuit(4, 5, 10, seed=3)
+    o = [16, 17, 18, 19]
+    cb = wl.closed_bitstrings(20, o, 1000, seed=4)
+    ref = sv.group_amplitudes(c, o, cb)
+    probe = lf.Plan(c, o, cb, dtype="chalf", max_log2=20, chalf_min_log2=8)
+    dims, _, _ = probe.steps()
+    lines = []
+    for s in range(len(dims)):
+        nz, nm, nn, nk = (int(x) for x in dims[s, :4])
+        if nz > 0 and dims[s, 5] == 1 and nn <= 5 and 2 <= nk <= 6 and nm >= 5:
+            lines.append(f"{nz} {nm} {nn} {nk} 1 1 {int(dims[s, 6])} 7\n")
+    probe.close()
+    assert lines, "no batched step of this plan fits the skinny kernel"
+    path = tmp_path / "tune.txt"
+    path.write_text("".join(lines))
+    lf.autotune_load(str(path))
+    outs = []
+    for keep in (False, True):
+        plan = lf.Plan(c, o, cb, dtype="chalf", max_log2=20, chalf_min_log2=8, keep_batch_order=keep).bind()
+        dims, _, _ = plan.steps()
+        out = plan.contract(0, plan.info()["n_slices"])
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+        plan.workspace = None
+        plan.close()
+    assert np.array_equal(outs[0], outs[1])
+    e = rel_err(outs[0], ref)
+    _say(f"rel_err {e:.2e}")
+    assert e < CHALF_TOL
+
+
 def test_batch_graph_matches_sequential(lf):
     """Many subtasks of uneven shape from several circuits: one recorded
     graph with parallel lanes gives bit-identical accumulators to per-item
