@@ -92,7 +92,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=45.0)
     ap.add_argument("--keep-batch-order", action="store_true",
-                    help="paper53: contract the closed strings in the given order (no sort by gathered bits)")
+                    help="contract the closed strings in the given order (no sort by gathered bits)")
     ap.add_argument("--dump-steps", default="", help="write per-step shapes and times (json)")
     ap.add_argument("--autotune-cache", default=None,
                     help="kernel choices to load (default: the committed MI355X choices)")
@@ -573,6 +573,7 @@ def main():
     # both arithmetics search with the complex-half step costs, so they share
     # one tree and one slicing (slice s is the same sub-network in both)
     kw["search_dtype"] = "chalf"
+    kw["keep_batch_order"] = args.keep_batch_order
     plan = lf.Plan(circ, openq, cb, dtype=args.dtype, max_log2=spec["max_log2"],
                    launch=args.launch, check_overflow=False, **kw)
     info = plan.info()
@@ -702,7 +703,8 @@ def main():
         "config": {"workload": args.workload, "qubits": circ.n_qubits, "cycles": spec["cycles"],
                    "open_qubits": len(openq), "closed_strings": len(cb),
                    "slices_total": n_slices, "slices_per_step": S,
-                   "max_log2_intermediate": info["max_log2_intermediate"]},
+                   "max_log2_intermediate": info["max_log2_intermediate"],
+                   "batch_order": "given" if args.keep_batch_order else "sorted by gathered bits"},
         "algorithmic_tflops": value * per_slice_flops / 1e12,
         "mfma_frac_algorithmic": value * per_slice_flops / 1e12 /
                                   (MI355X["fp16_tflops"] if args.dtype == "chalf" else MI355X["fp32_tflops"]),

@@ -56,10 +56,12 @@ template <> struct CIO<_Float16> {
     re = float(v[0]);
     im = float(v[1]);
   }
+  // values beyond the half range are clamped to +-HALF_MAX (NaN to 0) and
+  // counted; written without branches (a median of three and selects)
   __device__ static __forceinline__ unsigned store(_Float16* p, int64_t i, float re, float im) {
-    unsigned bad = 0;
-    if (!(fabsf(re) <= HALF_MAX)) { bad = 1; re = (re != re) ? 0.0f : copysignf(HALF_MAX, re); }
-    if (!(fabsf(im) <= HALF_MAX)) { bad = 1; im = (im != im) ? 0.0f : copysignf(HALF_MAX, im); }
+    const unsigned bad = unsigned(!(fabsf(re) <= HALF_MAX)) | unsigned(!(fabsf(im) <= HALF_MAX));
+    re = re != re ? 0.0f : __builtin_amdgcn_fmed3f(re, -HALF_MAX, HALF_MAX);
+    im = im != im ? 0.0f : __builtin_amdgcn_fmed3f(im, -HALF_MAX, HALF_MAX);
     f16x2 v;
     v[0] = (_Float16)re;
     v[1] = (_Float16)im;
@@ -723,8 +725,9 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
           lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
           // saturation counts only values that are stored (not the
           // calibration pass, which runs unscaled)
-          if (!(fabsf(re) <= HALF_MAX)) { lsat += a.amax_only ? 0 : 1; re = (re != re) ? 0.0f : copysignf(HALF_MAX, re); }
-          if (!(fabsf(im) <= HALF_MAX)) { lsat += a.amax_only ? 0 : 1; im = (im != im) ? 0.0f : copysignf(HALF_MAX, im); }
+          lsat += a.amax_only ? 0u : unsigned(!(fabsf(re) <= HALF_MAX)) + unsigned(!(fabsf(im) <= HALF_MAX));
+          re = re != re ? 0.0f : __builtin_amdgcn_fmed3f(re, -HALF_MAX, HALF_MAX);
+          im = im != im ? 0.0f : __builtin_amdgcn_fmed3f(im, -HALF_MAX, HALF_MAX);
           f16x2 h;
           h[0] = (_Float16)re;
           h[1] = (_Float16)im;
@@ -1157,8 +1160,9 @@ __global__ void __launch_bounds__(64 * NW, STAGES == 2 ? 2 : 1) gett_mfma_dma(Ge
           const int nl = wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
           float re = acc[bn][0][bm][v] * a.scale, im = acc[bn][1][bm][v] * a.scale;
           lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
-          if (!(fabsf(re) <= HALF_MAX)) { lsat += a.amax_only ? 0 : 1; re = (re != re) ? 0.0f : copysignf(HALF_MAX, re); }
-          if (!(fabsf(im) <= HALF_MAX)) { lsat += a.amax_only ? 0 : 1; im = (im != im) ? 0.0f : copysignf(HALF_MAX, im); }
+          lsat += a.amax_only ? 0u : unsigned(!(fabsf(re) <= HALF_MAX)) + unsigned(!(fabsf(im) <= HALF_MAX));
+          re = re != re ? 0.0f : __builtin_amdgcn_fmed3f(re, -HALF_MAX, HALF_MAX);
+          im = im != im ? 0.0f : __builtin_amdgcn_fmed3f(im, -HALF_MAX, HALF_MAX);
           f16x2 h;
           h[0] = (_Float16)re;
           h[1] = (_Float16)im;
@@ -1309,6 +1313,12 @@ __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) 
   };
   auto offA = [&](int64_t z) { return lane64(myA, int(z - z0)); };
   auto offB = [&](int64_t z) { return lane64(myB, int(z - z0)); };
+  // result offsets: of the entries (one lane each, as above) and of this
+  // lane's rows, which are the same for every entry
+  const int64_t myC = scatter_bits(zl, a.cz, a.nz);
+  int64_t cbm[GPW];
+#pragma unroll
+  for (int g = 0; g < GPW; ++g) cbm[g] = scatter_bits(m0 + g * 32 + (lane & 31), a.cm, a.nm);
   // raw B words of an entry (complex-half: 8 halves; complex64: 8 floats in two words)
   auto load_b = [&](int64_t bz, uint4 (&rb)[NF][S][BW]) __attribute__((always_inline)) {
 #pragma unroll
@@ -1391,6 +1401,9 @@ __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) 
   // entry's MFMAs, so their latency overlaps the arithmetic and the stores.
   // Waves of several groups reload A in place, only where the block changes.
   constexpr bool PIPE_A = GPW == 1;
+  // calibration pass: the running maximum only; otherwise store (the
+  // maximum is not needed then)
+  const bool store_all = !a.amax_only;
   uint4 rb[NF][S][BW];
   f16x8 af[GPW][S], an[GPW][S];
   float lmax = 0.0f;
@@ -1414,7 +1427,7 @@ __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) 
       if constexpr (PIPE_A) {
         if (nA != curA) load_a(nA, an);
       }
-      const int64_t czv = scatter_bits(z, a.cz, a.nz);
+      const int64_t czv = lane64(myC, zi);
 #pragma unroll
       for (int g = 0; g < GPW; ++g) {
         f32x16 acc[NF];
@@ -1429,17 +1442,20 @@ __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) 
             acc[f] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[f][st], af[g][st], acc[f], 0, 0, 0);
             if constexpr (SPLIT) acc[f] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[st], af[g][st], acc[f], 0, 0, 0);
           }
-        const int64_t m = m0 + g * 32 + (lane & 31);
-        const int64_t cb = czv + scatter_bits(m, a.cm, a.nm);
+        const int64_t cb = czv + cbm[g];
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
           for (int v = 0; v < 16; v += 2) {
+            // rows 8 (v / 4) .. of the fragment: none of them is a result row
+            // when 16 f + 4 (v / 4) >= N (the same in every lane)
+            if (16 * f + 4 * (v >> 2) >= N) break;
             const int nl = 16 * f + ((8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1);
-            if (nl >= N) continue;
             const float re = acc[f][v] * a.scale, im = acc[f][v + 1] * a.scale;
-            lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
-            if (!a.amax_only) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
+            if (nl < N) {
+              if (store_all) lsat += CIO<TO>::store(C, cb + cnT[nl], re, im);
+              else lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+            }
           }
       }
       if (nA != curA) {
