@@ -1258,7 +1258,7 @@ __global__ void __launch_bounds__(64 * NW, STAGES == 2 ? 2 : 1) gett_mfma_dma(Ge
 // to the next, so in a batch sorted by the closed bits of a gathered operand
 // each of its blocks is read once per run of entries that share it instead
 // of once per entry.
-template <typename TB, typename TO, int KC, int GPW, int NF = 1, int ZC = 1, int NSB = 0>
+template <typename TB, typename TO, int KC, int GPW, int NF = 1, int ZC = 1, int NSB = 0, int PACK = 1>
 __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) {
   constexpr int S = KC >= 8 ? KC / 8 : 1;   // k steps of 16 reals
   constexpr bool SPLIT = std::is_same<TB, float>::value;
@@ -1266,6 +1266,7 @@ __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) 
   static_assert(NF == 1 || (NF == 2 && !SPLIT), "two B' fragments: complex-half B only");
   static_assert(ZC >= 1 && ZC <= 64, "entries per wave: one lane each for their offsets");
   static_assert(NSB == 0 || (!SPLIT && NF == 1 && NSB <= 16), "staged B: complex-half, one fragment");
+  static_assert(PACK == 1 || (NSB > 0 && ZC % PACK == 0), "packed entries read B from the staged copy");
   constexpr int RW = KC >= 4 ? KC / 4 + 1 : 2;   // 16-byte words per staged B row (one of padding)
   __shared__ int64_t cnT[16 * NF];
   __shared__ uint4 sB[NSB > 0 ? ZC * NSB * RW : 1];
@@ -1408,6 +1409,93 @@ __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) 
   f16x8 af[GPW][S], an[GPW][S];
   float lmax = 0.0f;
   unsigned lsat = 0;
+  if constexpr (PACK > 1) {
+    // N <= 8: PACK = 16 / N consecutive entries that share their A block go
+    // through one B' fragment together (entry j of the pack in B' rows
+    // 2N j .. 2N j + 2N - 1), so the MFMAs and the B' operand work of a pack
+    // cost what one entry's did.  A pack whose entries differ in A is done
+    // entry by entry.
+    auto shfl64 = [](int64_t v, int src) {
+      return int64_t((uint64_t(uint32_t(__shfl(int(uint64_t(v) >> 32), src))) << 32) |
+                     uint32_t(__shfl(int(v), src)));
+    };
+    auto emit = [&](int g, const f32x16& acc, int e_fixed) __attribute__((always_inline)) {
+#pragma unroll
+      for (int v = 0; v < 16; v += 2) {
+        const int np = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        int e, nl;
+        if (e_fixed >= 0) {
+          e = e_fixed;
+          nl = np >> 1;
+          if (4 * (v >> 2) >= N) break;   // no result row in this row group (all lanes)
+        } else {
+          e = np / (2 * N);
+          nl = (np % (2 * N)) >> 1;
+        }
+        const float re = acc[v] * a.scale, im = acc[v + 1] * a.scale;
+        if (nl < N) {
+          const int64_t cz = e_fixed >= 0 ? lane64(myC, e) : shfl64(myC, e);
+          if (store_all) lsat += CIO<TO>::store(C, cz + cbm[g] + cnT[nl], re, im);
+          else lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
+        }
+      }
+    };
+    if (z0 < Z) {
+      int64_t curA = -1;
+      const int np = lane & 31;
+      for (int p = 0; p < ZC / PACK; ++p) {
+        const int e0 = p * PACK;
+        const int64_t a0 = offA(z0 + e0);
+        bool same = true;
+#pragma unroll
+        for (int j = 1; j < PACK; ++j) same = same && offA(z0 + e0 + j) == a0;
+        if (same) {
+          if (a0 != curA) {
+            load_a(a0, af);
+            curA = a0;
+          }
+          const int je = np / (2 * N), nr = (np % (2 * N)) >> 1;
+          f16x8 bpk[S];
+#pragma unroll
+          for (int st = 0; st < S; ++st) {
+            const int kc = st * 8 + kq;
+            bpk[st] = bprime_frag(kc < KC ? sB[((e0 + je) * NSB + nr) * RW + kc / 4] : make_uint4(0, 0, 0, 0), bp);
+          }
+#pragma unroll
+          for (int g = 0; g < GPW; ++g) {
+            f32x16 acc;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+#pragma unroll
+            for (int st = 0; st < S; ++st) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(bpk[st], af[g][st], acc, 0, 0, 0);
+            emit(g, acc, -1);
+          }
+        } else {
+          for (int j = 0; j < PACK; ++j) {
+            const int e = e0 + j;
+            const int64_t ae = offA(z0 + e);
+            if (ae != curA) {
+              load_a(ae, af);
+              curA = ae;
+            }
+            load_b_lds(e, rb);
+            form_b(rb);
+#pragma unroll
+            for (int g = 0; g < GPW; ++g) {
+              f32x16 acc;
+#pragma unroll
+              for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+#pragma unroll
+              for (int st = 0; st < S; ++st) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[0][st], af[g][st], acc, 0, 0, 0);
+              emit(g, acc, e);
+            }
+          }
+        }
+      }
+    }
+    block_amax_sat(lmax, lsat, a.amax, a.sat);
+    return;
+  }
   if (z0 < Z) {
     int64_t curB = offB(z0), curA = offA(z0);
     if constexpr (NSB > 0) load_b_lds(0, rb);
@@ -1486,10 +1574,14 @@ static hipError_t launch_skinny_g(const GettArgs& a, hipStream_t s) {
     const int64_t blocks = (n_waves + 3) / 4;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     // B staged in LDS per chunk when every block's four waves share a chunk
+    // and, for N <= 8, 16 / N entries through one B' fragment
     if constexpr (!std::is_same<TB, float>::value && NF == 1) {
       if (slabs % 4 == 0 && a.nn <= 3) {
-        hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 16, 8>), dim3(unsigned(blocks)), dim3(256), 0, s, a,
-                           n_waves);
+        const dim3 g(static_cast<unsigned>(blocks)), b(256);
+        if (a.nn == 0) hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 16, 8, 16>), g, b, 0, s, a, n_waves);
+        else if (a.nn == 1) hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 16, 8, 8>), g, b, 0, s, a, n_waves);
+        else if (a.nn == 2) hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 16, 8, 4>), g, b, 0, s, a, n_waves);
+        else hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 16, 8, 2>), g, b, 0, s, a, n_waves);
         return hipGetLastError();
       }
     }
