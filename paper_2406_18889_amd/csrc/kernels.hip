@@ -58,14 +58,20 @@ template <> struct CIO<_Float16> {
   }
   // values beyond the half range are clamped to +-HALF_MAX (NaN to 0) and
   // counted; written without branches (a median of three and selects)
-  __device__ static __forceinline__ unsigned store(_Float16* p, int64_t i, float re, float im) {
-    const unsigned bad = unsigned(!(fabsf(re) <= HALF_MAX)) | unsigned(!(fabsf(im) <= HALF_MAX));
+  __device__ static __forceinline__ uint32_t pack(float re, float im, unsigned& bad) {
+    bad = unsigned(!(fabsf(re) <= HALF_MAX)) | unsigned(!(fabsf(im) <= HALF_MAX));
     re = re != re ? 0.0f : __builtin_amdgcn_fmed3f(re, -HALF_MAX, HALF_MAX);
     im = im != im ? 0.0f : __builtin_amdgcn_fmed3f(im, -HALF_MAX, HALF_MAX);
     f16x2 v;
     v[0] = (_Float16)re;
     v[1] = (_Float16)im;
-    reinterpret_cast<f16x2*>(p)[i] = v;
+    uint32_t w;
+    __builtin_memcpy(&w, &v, 4);
+    return w;
+  }
+  __device__ static __forceinline__ unsigned store(_Float16* p, int64_t i, float re, float im) {
+    unsigned bad;
+    reinterpret_cast<uint32_t*>(p)[i] = pack(re, im, bad);
     return bad;
   }
 };
@@ -697,6 +703,17 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
     constexpr int LM = 8, LN = BN == 128 ? 7 : (BN == 64 ? 6 : 5), LT = LM + LN;
     constexpr int PER = (BM * BN) / 256;   // elements per thread
     uint32_t* stage = reinterpret_cast<uint32_t*>(smem);
+    if (a.amax_only) {
+      // calibration pass: the running maximum only, nothing is stored
+#pragma unroll
+      for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+        for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) lmax = fmaxf(lmax, fabsf(acc[bn][bm][v] * a.scale));
+      block_amax_sat(lmax, 0u, a.amax, a.sat);
+      return;
+    }
     __shared__ int64_t sStv[LT];   // the tile's bit strides in ascending order (stable)
     __shared__ int sBit[LT];       // and which tile bit each is (0..LM-1 m, LM.. n)
     if (tid < LT) {
@@ -722,10 +739,7 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
         for (int v = 0; v < 16; v += 2) {
           const int nl = (wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1;
           float re = acc[bn][bm][v] * a.scale, im = acc[bn][bm][v + 1] * a.scale;
-          lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
-          // saturation counts only values that are stored (not the
-          // calibration pass, which runs unscaled)
-          lsat += a.amax_only ? 0u : unsigned(!(fabsf(re) <= HALF_MAX)) + unsigned(!(fabsf(im) <= HALF_MAX));
+          lsat += unsigned(!(fabsf(re) <= HALF_MAX)) + unsigned(!(fabsf(im) <= HALF_MAX));
           re = re != re ? 0.0f : __builtin_amdgcn_fmed3f(re, -HALF_MAX, HALF_MAX);
           im = im != im ? 0.0f : __builtin_amdgcn_fmed3f(im, -HALF_MAX, HALF_MAX);
           f16x2 h;
@@ -1134,6 +1148,19 @@ __global__ void __launch_bounds__(64 * NW, STAGES == 2 ? 2 : 1) gett_mfma_dma(Ge
     static_assert((1 << LO) == NT && PER <= NT, "thread bits of the write-out");
     static_assert(BM * SROW * 4 <= int(sizeof(smem)), "staged tile fits the operand stages");
     uint32_t* stage = reinterpret_cast<uint32_t*>(smem);
+    if (a.amax_only) {
+      // calibration pass: the running maximum only, nothing is stored
+#pragma unroll
+      for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) lmax = fmaxf(lmax, fabsf(acc[bn][p][bm][v] * a.scale));
+      block_amax_sat(lmax, 0u, a.amax, a.sat);
+      return;
+    }
     __shared__ int64_t sStv[LT];   // the tile's bit strides in ascending order (stable)
     __shared__ int sBit[LT];       // and which tile bit each is
     if (tid < LT) {
@@ -1159,8 +1186,7 @@ __global__ void __launch_bounds__(64 * NW, STAGES == 2 ? 2 : 1) gett_mfma_dma(Ge
         for (int v = 0; v < 16; ++v) {
           const int nl = wn * 32 * WN + bn * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
           float re = acc[bn][0][bm][v] * a.scale, im = acc[bn][1][bm][v] * a.scale;
-          lmax = fmaxf(lmax, fmaxf(fabsf(re), fabsf(im)));
-          lsat += a.amax_only ? 0u : unsigned(!(fabsf(re) <= HALF_MAX)) + unsigned(!(fabsf(im) <= HALF_MAX));
+          lsat += unsigned(!(fabsf(re) <= HALF_MAX)) + unsigned(!(fabsf(im) <= HALF_MAX));
           re = re != re ? 0.0f : __builtin_amdgcn_fmed3f(re, -HALF_MAX, HALF_MAX);
           im = im != im ? 0.0f : __builtin_amdgcn_fmed3f(im, -HALF_MAX, HALF_MAX);
           f16x2 h;
@@ -1258,7 +1284,7 @@ __global__ void __launch_bounds__(64 * NW, STAGES == 2 ? 2 : 1) gett_mfma_dma(Ge
 // to the next, so in a batch sorted by the closed bits of a gathered operand
 // each of its blocks is read once per run of entries that share it instead
 // of once per entry.
-template <typename TB, typename TO, int KC, int GPW, int NF = 1, int ZC = 1, int NSB = 0, int PACK = 1>
+template <typename TB, typename TO, int KC, int GPW, int NF = 1, int ZC = 1, int NSB = 0, int PACK = 1, int STG = 0>
 __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) {
   constexpr int S = KC >= 8 ? KC / 8 : 1;   // k steps of 16 reals
   constexpr bool SPLIT = std::is_same<TB, float>::value;
@@ -1267,6 +1293,14 @@ __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) 
   static_assert(ZC >= 1 && ZC <= 64, "entries per wave: one lane each for their offsets");
   static_assert(NSB == 0 || (!SPLIT && NF == 1 && NSB <= 16), "staged B: complex-half, one fragment");
   static_assert(PACK == 1 || (NSB > 0 && ZC % PACK == 0), "packed entries read B from the staged copy");
+  static_assert(STG == 0 || (GPW == 1 && NF == 2 && PACK == 1 && std::is_same<TO, _Float16>::value),
+                "staged write-out: one 32 x 32 complex-half block per entry");
+  // STG: each entry's 32 x 32 result is one contiguous 4 KB block of C
+  // (checked at launch); the wave writes it to LDS at its place in the block
+  // (word o at o ^ 4 ((o >> 6) & 15), so the scattered writes of a wave fall
+  // in distinct banks) and copies it out in 16-byte pieces, four store
+  // instructions of 1 KB each instead of 16 scattered ones
+  __shared__ uint32_t stg[STG ? 4 * 1024 : 1];
   constexpr int RW = KC >= 4 ? KC / 4 + 1 : 2;   // 16-byte words per staged B row (one of padding)
   __shared__ int64_t cnT[16 * NF];
   __shared__ uint4 sB[NSB > 0 ? ZC * NSB * RW : 1];
@@ -1531,6 +1565,30 @@ __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) 
             if constexpr (SPLIT) acc[f] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[st], af[g][st], acc[f], 0, 0, 0);
           }
         const int64_t cb = czv + cbm[g];
+        if constexpr (STG) {
+          if (store_all) {
+            uint32_t* sw = stg + (threadIdx.x >> 6) * 1024;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+              for (int v = 0; v < 16; v += 2) {
+                const int nl = 16 * f + ((8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) >> 1);
+                const int o = int(cbm[g] + cnT[nl]);
+                unsigned bad;
+                sw[o ^ (((o >> 6) & 15) << 2)] = CIO<_Float16>::pack(acc[f][v] * a.scale, acc[f][v + 1] * a.scale, bad);
+                lsat += bad;
+              }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            uint4* Cq = reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(C) + czv);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int o = 4 * lane + 256 * r;
+              Cq[lane + 64 * r] = *reinterpret_cast<const uint4*>(sw + (o ^ (((o >> 6) & 15) << 2)));
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            continue;
+          }
+        }
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -1565,6 +1623,20 @@ __global__ void __launch_bounds__(256) gett_skinny(GettArgs a, int64_t n_waves) 
 
 // waves: (2^nz / ZC) entry chunks x (M / 32 GPW) slabs; ZC = 16 consecutive
 // entries per wave for batched steps with at least 2^8 entries, else one
+// whether every entry's result is one contiguous block: the m and n strides
+// are 1, 2, 4, ... in some order
+static bool entry_block_contiguous(const GettArgs& a) {
+  uint64_t seen = 0;
+  const int nb = a.nm + a.nn;
+  if (nb > 62) return false;
+  for (int i = 0; i < nb; ++i) {
+    const int64_t v = i < a.nm ? a.cm[i] : a.cn[i - a.nm];
+    if (v <= 0 || (v & (v - 1)) || v >= (int64_t(1) << nb)) return false;
+    seen |= uint64_t(v);
+  }
+  return seen == (uint64_t(1) << nb) - 1;
+}
+
 template <typename TB, typename TO, int KC, int GPW, int NF>
 static hipError_t launch_skinny_g(const GettArgs& a, hipStream_t s) {
   if (((int64_t(1) << a.nm) % (32 * GPW)) != 0) return hipErrorInvalidValue;
@@ -1582,6 +1654,13 @@ static hipError_t launch_skinny_g(const GettArgs& a, hipStream_t s) {
         else if (a.nn == 1) hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 16, 8, 8>), g, b, 0, s, a, n_waves);
         else if (a.nn == 2) hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 16, 8, 4>), g, b, 0, s, a, n_waves);
         else hipLaunchKernelGGL((gett_skinny<TB, TO, KC, GPW, NF, 16, 8, 2>), g, b, 0, s, a, n_waves);
+        return hipGetLastError();
+      }
+    }
+    if constexpr (GPW == 1 && NF == 2 && std::is_same<TO, _Float16>::value) {
+      if (a.nm == 5 && a.nn == 5 && entry_block_contiguous(a)) {
+        hipLaunchKernelGGL((gett_skinny<TB, TO, KC, 1, 2, 16, 0, 1, 1>), dim3(unsigned(blocks)), dim3(256), 0, s, a,
+                           n_waves);
         return hipGetLastError();
       }
     }

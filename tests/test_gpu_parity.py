@@ -222,7 +222,10 @@ def test_pair_chalf_layouts(lf, kernel, layout):
 # The streaming kernels over the same layouts.
 @pytest.mark.parametrize("kernel", [0, 3, 7])
 @pytest.mark.parametrize("layout", ["n_fastest", "m_fastest", "z_fastest", "split_pair"])
-@pytest.mark.parametrize("shape", [(1, 9, 4, 2), (2, 8, 2, 4), (1, 10, 3, 3)])
+@pytest.mark.parametrize("shape", [(1, 9, 4, 2), (2, 8, 2, 4), (1, 10, 3, 3),
+                                   # 32 x 32 blocks per entry: staged write-out when
+                                   # each entry's block is contiguous (n or m fastest)
+                                   (8, 5, 5, 5), (3, 5, 5, 3), (9, 5, 5, 6)])
 def test_pair_chalf_streaming_layouts(lf, kernel, layout, shape):
     nz, nm, nn, nk = shape
     if not _applicable(kernel, "chalf", shape):
