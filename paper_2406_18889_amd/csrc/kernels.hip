@@ -826,8 +826,8 @@ __global__ void __launch_bounds__(256, MINB) gett_mfma_big(GettArgs a) {
 
 // ------------------------------------------------------------ DMA-fed MFMA
 // The 256 m x 128 n complex tile, run by eight waves (two per SIMD, each
-// 64 m x 64 n, the accumulators in 128 VGPRs) so that one wave's MFMAs cover
-// the other's LDS waits, or by four (one per SIMD, 128 m x 64 n, the
+// 128 m x 32 n, the accumulators in 128 VGPRs) so that one wave's MFMAs
+// cover the other's LDS waits, or by four (one per SIMD, 128 m x 64 n, the
 // accumulators in AGPRs).  The real and imaginary parts of C are separate
 // 32 x 32 MFMA blocks that share the A fragment: each lane reads one whole
 // B row chunk, and both operand forms of it, (Br, -Bi) and (Bi, Br), are
@@ -865,7 +865,7 @@ __device__ __forceinline__ void wait_loads_barrier() {
   if constexpr (N == 15) asm volatile("s_waitcnt vmcnt(15) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// NW = 8: eight waves (two per SIMD), each 64 m x 64 n, 8 MFMAs per k step,
+// NW = 8: eight waves (two per SIMD), each 128 m x 32 n, 8 MFMAs per k step,
 // 128 accumulator registers.  NW = 4: four waves (one per SIMD), each 128 m x
 // 64 n, 16 MFMAs per k step, 256 accumulator registers (AGPRs): fewer LDS
 // bytes and VALU operations per MFMA, and the waits must be hidden by the
@@ -883,8 +883,12 @@ __global__ void __launch_bounds__(64 * NW, STAGES == 2 ? 2 : 1) gett_mfma_dma(Ge
   static_assert(NW == 4 || NW == 8, "wave count");
   static_assert((BM == 256 && STAGES == 3) || (BM == 128 && STAGES == 2 && NW == 4), "tile forms");
   constexpr int NT = 64 * NW;
-  constexpr int MW = NW / 2;                     // waves along m (two along n)
-  constexpr int WM = BM / (32 * MW), WN = 2;     // 32 x 32 MFMA tiles per wave in m and complex n
+  // waves along m (the rest along n): eight waves as 2 x 4, each 128 m x
+  // 32 n, so that a wave forms the B' operands of one 32-row block of B per
+  // k step for its 8 MFMAs (one VALU operation per MFMA instead of two, for
+  // one more LDS read); four waves as 2 x 2
+  constexpr int MW = 2;
+  constexpr int WM = BM / (32 * MW), WN = DMA_BN / (32 * (NW / MW));   // 32 x 32 MFMA tiles per wave
   constexpr int SA = BM * 128;                   // bytes of the A tile of a stage
   constexpr int STAGE = (BM + DMA_BN) * 128;     // bytes per stage
   constexpr int A_LOADS = BM * 128 / 1024 / NW, B_LOADS = DMA_BN * 128 / 1024 / NW;
