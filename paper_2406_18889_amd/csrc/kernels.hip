@@ -872,7 +872,7 @@ __device__ __forceinline__ void wait_loads_barrier() {
 // order of one wave's instructions alone.
 //
 // BM = 128, STAGES = 2 (kernels 16 and 17): the 128 m x 128 n tile on four
-// waves (each 64 m x 64 n, as in the eight-wave form) with two operand
+// waves (each 128 m x 32 n, as in the eight-wave form) with two operand
 // stages, so that its LDS (68 KB) lets two workgroups share a CU: one
 // workgroup's first loads and write-out run while the other computes, which
 // pays on steps with a short K where those fixed costs are a large share.
@@ -883,11 +883,12 @@ __global__ void __launch_bounds__(64 * NW, STAGES == 2 ? 2 : 1) gett_mfma_dma(Ge
   static_assert(NW == 4 || NW == 8, "wave count");
   static_assert((BM == 256 && STAGES == 3) || (BM == 128 && STAGES == 2 && NW == 4), "tile forms");
   constexpr int NT = 64 * NW;
-  // waves along m (the rest along n): eight waves as 2 x 4, each 128 m x
-  // 32 n, so that a wave forms the B' operands of one 32-row block of B per
-  // k step for its 8 MFMAs (one VALU operation per MFMA instead of two, for
-  // one more LDS read); four waves as 2 x 2
-  constexpr int MW = 2;
+  // waves along m (the rest along n): eight waves as 2 x 4 and the 128-row
+  // tile's four as 1 x 4, each 128 m x 32 n, so that a wave forms the B'
+  // operands of one 32-row block of B per k step for its 8 MFMAs (one VALU
+  // operation per MFMA instead of two, for one more LDS read); the 256-row
+  // tile's four waves as 2 x 2
+  constexpr int MW = (NW == 4 && BM == 128) ? 1 : 2;
   constexpr int WM = BM / (32 * MW), WN = DMA_BN / (32 * (NW / MW));   // 32 x 32 MFMA tiles per wave
   constexpr int SA = BM * 128;                   // bytes of the A tile of a stage
   constexpr int STAGE = (BM + DMA_BN) * 128;     // bytes per stage
