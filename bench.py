@@ -113,6 +113,10 @@ def parse():
     ap.add_argument("--copy-pmc", nargs="*", default=[],
                     help="counter CSVs of a plain 1 GiB device copy (FETCH_SIZE/WRITE_SIZE scale)")
     ap.add_argument("--summary-out", default="", help="--summarize-pmc: write json here")
+    ap.add_argument("--summarize-trace", default="", metavar="CSV",
+                    help="rocprofv3 kernel trace: time per kernel over the last whole slice (between the last "
+                         "two accumulate launches) and the share of the traced time with 1, 2, ... kernels "
+                         "in flight")
     return ap.parse_args()
 
 
@@ -543,10 +547,52 @@ def summarize_pmc(args):
     print(json.dumps(out))
 
 
+def summarize_trace(args):
+    """Per-kernel time of the last whole slice of a rocprofv3 kernel trace
+    (the dispatches after the second-to-last accumulate launch, up to and
+    including the last), its longest dispatches, and how much of the traced
+    span had 1, 2, ... kernels executing at once (concurrent lanes)."""
+    import csv
+    from collections import defaultdict
+    with open(args.summarize_trace) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
+    dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    short = lambda r: r["Kernel_Name"].split("(")[0][:90]
+    out = {"dispatches": len(rows)}
+    acc = [i for i, r in enumerate(rows) if "accumulate_kernel" in r["Kernel_Name"]]
+    if len(acc) >= 2:
+        seg = rows[acc[-2] + 1:acc[-1] + 1]
+        per = defaultdict(lambda: [0, 0.0])
+        for r in seg:
+            per[short(r)][0] += 1
+            per[short(r)][1] += dur(r)
+        out["slice"] = {"kernels": len(seg), "kernel_ms": sum(dur(r) for r in seg),
+                        "span_ms": (int(seg[-1]["End_Timestamp"]) - int(rows[acc[-2]]["End_Timestamp"])) / 1e6,
+                        "by_kernel": sorted(([k, v[0], v[1]] for k, v in per.items()), key=lambda x: -x[2]),
+                        "longest": [[short(r), dur(r), int(r["Grid_Size_X"])]
+                                    for r in sorted(seg, key=lambda r: -dur(r))[:8]]}
+    ev = []
+    for r in rows:
+        ev.append((int(r["Start_Timestamp"]), 1))
+        ev.append((int(r["End_Timestamp"]), -1))
+    ev.sort()
+    busy = defaultdict(float)
+    cur, last = 0, ev[0][0] if ev else 0
+    for t, d in ev:
+        if cur > 0:
+            busy[cur] += (t - last) / 1e6
+        cur += d
+        last = t
+    out["ms_with_k_kernels_in_flight"] = {str(k): v for k, v in sorted(busy.items())}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.summarize_pmc:
         return summarize_pmc(args)
+    if args.summarize_trace:
+        return summarize_trace(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
