@@ -134,6 +134,9 @@ typedef struct lf_plan_opts {
                                     block become neighbours, so its reads hit in cache);
                                     out_amps rows stay in the caller's order.  1: contract
                                     them in the given order */
+  int32_t group_small_steps;     /* 1 (default): consecutive small independent steps that
+                                    run on the streaming kernel go out as one launch
+                                    (results identical); 0: one launch per step */
 } lf_plan_opts;
 
 typedef struct lf_plan_info {
@@ -155,6 +158,10 @@ typedef struct lf_plan_info {
   double log2_total_macs;        /* all slices */
   uint64_t workspace_bytes;      /* device bytes lf_plan_bind_workspace needs */
   int32_t leaf_id_base;          /* first node id of an intermediate in lf_plan_tree */
+  int32_t n_step_groups;         /* launches that each run several small slice-dependent
+                                    steps (group_small_steps), as set up by the last
+                                    contraction; 0 before the first one */
+  int32_t n_grouped_steps;       /* the steps in them */
 } lf_plan_info;
 
 typedef struct lf_plan lf_plan;

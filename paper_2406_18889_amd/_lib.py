@@ -57,7 +57,8 @@ class lf_plan_opts(ctypes.Structure):
                 ("autotune", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("chalf_headroom_bits", ctypes.c_int32), ("overflow_policy", ctypes.c_int32),
                 ("chalf_exec_min_log2", ctypes.c_int32), ("mult", ctypes.c_int32),
-                ("autotune_cache", ctypes.c_char_p), ("keep_batch_order", ctypes.c_int32)]
+                ("autotune_cache", ctypes.c_char_p), ("keep_batch_order", ctypes.c_int32),
+                ("group_small_steps", ctypes.c_int32)]
 
 
 class lf_overflow_info(ctypes.Structure):
@@ -84,7 +85,8 @@ class lf_plan_info(ctypes.Structure):
                 ("macs_per_slice", ctypes.c_double), ("macs_invariant", ctypes.c_double),
                 ("bytes_per_slice", ctypes.c_double), ("bytes_invariant", ctypes.c_double),
                 ("log2_total_macs", ctypes.c_double), ("workspace_bytes", ctypes.c_uint64),
-                ("leaf_id_base", ctypes.c_int32)]
+                ("leaf_id_base", ctypes.c_int32), ("n_step_groups", ctypes.c_int32),
+                ("n_grouped_steps", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes)

@@ -58,7 +58,7 @@ class Plan:
                  restarts: int = 1, chalf_headroom_bits: int = 4,
                  overflow_policy: str = "recalibrate", chalf_exec_min_log2: int = -1,
                  mult: str = "auto", autotune_cache: Optional[str] = None,
-                 keep_batch_order: bool = False):
+                 keep_batch_order: bool = False, group_small_steps: bool = True):
         lib = _lib.load()
         self._lib = lib
         self._handle = ctypes.c_void_p()
@@ -95,6 +95,7 @@ class Plan:
         cache = autotune_cache.encode() if autotune_cache else None
         opts.autotune_cache = cache
         opts.keep_batch_order = int(bool(keep_batch_order))
+        opts.group_small_steps = int(bool(group_small_steps))
         c, arr = _circuit_struct(circuit)
         openq = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         cb = np.ascontiguousarray(self.closed_bits)

@@ -70,6 +70,22 @@ enum KernelId : int {
 // pairs).  a_dt != b_dt is allowed only as a complex-half A with a
 // complex64 B, on the streaming kernels and K_SKINNY.
 hipError_t launch_gett(int kernel, int a_dt, int b_dt, int out_dt, const GettArgs& a, hipStream_t s);
+
+// One step of a grouped launch of small streaming steps (the streaming
+// one-row-per-thread kernel): its arguments, its operand and result types
+// (combo = a_dt | b_dt << 1 | out_dt << 2, 1 = complex-half; B complex-half
+// only with A complex-half) and its block count.
+struct GroupStep {
+  GettArgs a;
+  int32_t combo;
+  int32_t pad;
+  int64_t blocks;
+};
+// blocks of the streaming kernel's launch for these arguments
+int64_t thin_blocks(const GettArgs& a);
+// the n steps of tab (device memory) in one launch of total_blocks blocks
+// (the sum of their block counts)
+hipError_t launch_thin_group(const GroupStep* tab, int n, int64_t total_blocks, hipStream_t s);
 bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk);
 
 // Copies of the slice-dependent blocks of leaf tensors.

@@ -96,8 +96,10 @@ __device__ __forceinline__ void block_amax_sat(float local_max, unsigned local_s
 // steps with a narrow side (a large tensor against a gate or small branch),
 // which are bound by HBM traffic: every A element is read once, every C
 // element written once.
+// The body takes the block number and the block count explicitly, so that a
+// grouped launch can run several steps' blocks (see gett_thin_group).
 template <typename TA, typename TB, typename TO>
-__global__ void __launch_bounds__(256) gett_thin(GettArgs a) {
+__device__ __forceinline__ void thin_body(const GettArgs& a, int64_t blk, int64_t nblk) {
   constexpr int NB = 8;
   const int64_t M = int64_t(1) << a.nm, N = int64_t(1) << a.nn, K = int64_t(1) << a.nk;
   const int64_t rows = (int64_t(1) << a.nz) * M;
@@ -109,8 +111,7 @@ __global__ void __launch_bounds__(256) gett_thin(GettArgs a) {
   TO* C = static_cast<TO*>(a.C);
   float lmax = 0.0f;
   unsigned lsat = 0;
-  for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < rows;
-       r += int64_t(gridDim.x) * blockDim.x) {
+  for (int64_t r = blk * int64_t(blockDim.x) + threadIdx.x; r < rows; r += nblk * blockDim.x) {
     const int64_t z = r >> a.nm, m = r & (M - 1);
     const int64_t cbase = scatter_bits(z, a.cz, a.nz) + scatter_bits(m, a.cm, a.nm);
     const int64_t arow = (a.offA ? a.offA[z] : z * M * K) + m * K;
@@ -146,6 +147,47 @@ __global__ void __launch_bounds__(256) gett_thin(GettArgs a) {
     }
   }
   block_amax_sat(lmax, lsat, a.amax, a.sat);
+}
+
+template <typename TA, typename TB, typename TO>
+__global__ void __launch_bounds__(256) gett_thin(GettArgs a) {
+  thin_body<TA, TB, TO>(a, blockIdx.x, gridDim.x);
+}
+
+// Several independent small streaming steps in one launch: block b runs for
+// the step whose block range holds it.  A step of a few hundred rows costs
+// mostly its launch (a few microseconds each, one after another); grouped,
+// the steps' memory latencies overlap and the launch is paid once.
+__global__ void __launch_bounds__(256) gett_thin_group(const GroupStep* tab, int n) {
+  int64_t b = blockIdx.x;
+  int i = 0;
+  while (i + 1 < n && b >= tab[i].blocks) {
+    b -= tab[i].blocks;
+    ++i;
+  }
+  const GroupStep& g = tab[i];
+  switch (g.combo) {
+    case 0: thin_body<float, float, float>(g.a, b, g.blocks); break;
+    case 1: thin_body<_Float16, float, float>(g.a, b, g.blocks); break;
+    case 4: thin_body<float, float, _Float16>(g.a, b, g.blocks); break;
+    case 5: thin_body<_Float16, float, _Float16>(g.a, b, g.blocks); break;
+    case 3: thin_body<_Float16, _Float16, float>(g.a, b, g.blocks); break;
+    case 7: thin_body<_Float16, _Float16, _Float16>(g.a, b, g.blocks); break;
+    default: break;
+  }
+}
+
+int64_t thin_blocks(const GettArgs& a) {
+  const int64_t rows = (int64_t(1) << a.nz) << a.nm;
+  int64_t blocks = (rows + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  return blocks < 1 ? 1 : blocks;
+}
+
+hipError_t launch_thin_group(const GroupStep* tab, int n, int64_t total_blocks, hipStream_t s) {
+  if (n < 1 || total_blocks < 1 || total_blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gett_thin_group, dim3(unsigned(total_blocks)), dim3(256), 0, s, tab, n);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------- narrow
@@ -1840,9 +1882,7 @@ bool kernel_applicable(int kernel, int in_dt, int nz, int nm, int nn, int nk) {
 
 template <typename TA, typename TB, typename TO>
 static hipError_t launch_thin(const GettArgs& a, hipStream_t s) {
-  const int64_t rows = (int64_t(1) << a.nz) << a.nm;
-  int64_t blocks = (rows + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
+  const int64_t blocks = thin_blocks(a);
   hipLaunchKernelGGL((gett_thin<TA, TB, TO>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
   return hipGetLastError();
 }

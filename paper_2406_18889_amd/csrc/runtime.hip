@@ -93,6 +93,17 @@ struct lf_plan {
   // off_rows and maps root rows to out_amps rows.
   std::vector<int64_t> batch_src;
   int64_t off_rows = -1;
+  // grouped launches of small independent streaming steps: (first position
+  // in variant_steps, step count, blocks, first table entry); built after
+  // tuning and calibration for one generation and one timed kernel, the
+  // tables in the workspace at off_groups
+  struct Group { int first, count; int64_t blocks; int tab; };
+  std::vector<Group> groups;
+  std::vector<int> group_at;          // per position in variant_steps: group starting there, or -1
+  std::vector<lf::GroupStep> group_tab;
+  uint64_t groups_gen = ~0ull;
+  int groups_time_kernel = -2;
+  int64_t off_groups = 0;
   int64_t copy_max_n = 0;
   int64_t off_copies_tab = 0, off_sigma = 0, off_sat = 0, off_amax = 0;
   // off_sat holds the saturation counter (uint32) and, 8 bytes on, the first
@@ -365,6 +376,8 @@ std::string plan_memory(lf_plan* P) {
   cur += align_up(int64_t(sizeof(float)) * std::max<size_t>(1, hp.steps.size()));
   P->off_copies_tab = cur;
   cur += align_up(int64_t(sizeof(SliceCopy)) * std::max<size_t>(1, P->copies.size()));
+  P->off_groups = cur;
+  cur += align_up(int64_t(sizeof(GroupStep)) * std::max<size_t>(1, P->variant_steps.size()));
   P->ws_bytes = uint64_t(cur);
   return "";
 }
@@ -506,13 +519,92 @@ lf_status reserve_events(lf_plan* P, size_t pairs) {
   return LF_OK;
 }
 
+// Groups of consecutive slice-dependent steps that run on the streaming
+// kernel with at most 2^16 rows, none reading another's result or writing
+// over another's operands (the per-slice allocation packs buffers by
+// lifetime in step order, so a later step's result may take an earlier
+// step's dead operand), at most 16 per group.  Each group becomes one launch
+// of gett_thin_group; the steps' arguments are those of run_step.
+lf_status build_groups(lf_plan* P, hipStream_t st) {
+  P->groups.clear();
+  P->group_tab.clear();
+  const int nv = int(P->variant_steps.size());
+  P->group_at.assign(size_t(nv), -1);
+  auto esize = [&](int n) { return int64_t(P->store_dt[size_t(n)] == 1 ? 4 : 8); };
+  auto overlap = [&](int x, int y) {
+    const int64_t x0 = P->off[size_t(x)], x1 = x0 + P->elems[size_t(x)] * esize(x);
+    const int64_t y0 = P->off[size_t(y)], y1 = y0 + P->elems[size_t(y)] * esize(y);
+    return x0 < y1 && y0 < x1;
+  };
+  auto small = [&](int s) {
+    const StepLayout& t = P->hp.steps[size_t(s)];
+    return t.kernel == K_THIN && P->time_kernel != K_THIN && t.nz + t.nm <= 16;
+  };
+  if (P->opts.group_small_steps) {
+    int i = 0;
+    while (i < nv) {
+      if (!small(P->variant_steps[size_t(i)])) { ++i; continue; }
+      int j = i + 1;
+      while (j < nv && j - i < 16 && small(P->variant_steps[size_t(j)])) {
+        const StepLayout& b = P->hp.steps[size_t(P->variant_steps[size_t(j)])];
+        bool ok = true;
+        for (int k = i; k < j && ok; ++k) {
+          const StepLayout& a = P->hp.steps[size_t(P->variant_steps[size_t(k)])];
+          ok = b.a != a.out && b.b != a.out && !overlap(b.out, a.a) && !overlap(b.out, a.b) &&
+               !overlap(b.out, a.out);
+        }
+        if (!ok) break;
+        ++j;
+      }
+      if (j - i >= 2) {
+        lf_plan::Group g{i, j - i, 0, int(P->group_tab.size())};
+        for (int k = i; k < j; ++k) {
+          const int s = P->variant_steps[size_t(k)];
+          const StepLayout& t = P->hp.steps[size_t(s)];
+          GroupStep e{};
+          e.a = step_args(P, s);
+          e.combo = P->store_dt[size_t(t.a)] | (P->store_dt[size_t(t.b)] << 1) | (P->store_dt[size_t(t.out)] << 2);
+          e.blocks = thin_blocks(e.a);
+          g.blocks += e.blocks;
+          P->group_tab.push_back(e);
+        }
+        P->group_at[size_t(i)] = int(P->groups.size());
+        P->groups.push_back(g);
+      }
+      i = j;
+    }
+  }
+  if (!P->group_tab.empty()) {
+    HIPCHK(hipMemcpyAsync(P->ws + P->off_groups, P->group_tab.data(), P->group_tab.size() * sizeof(GroupStep),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));   // the host table may change before the next build
+  }
+  P->groups_gen = P->generation;
+  P->groups_time_kernel = P->time_kernel;
+  return LF_OK;
+}
+
+bool groups_valid(const lf_plan* P) {
+  return P->groups_gen == P->generation && P->groups_time_kernel == P->time_kernel;
+}
+
 // timed: bracket the launches of kernel P->time_kernel with events on the
 // launch stream (stream mode only: events are not recorded into graphs)
 lf_status run_slice(lf_plan* P, const int64_t* sigma_dev, int64_t sigma, double* out,
                     hipStream_t stream, bool timed = false) {
   HIPCHK(launch_instantiate(reinterpret_cast<const SliceCopy*>(P->ws + P->off_copies_tab),
                             int(P->copies.size()), P->copy_max_n, P->ws, sigma_dev, sigma, stream));
-  for (int s : P->variant_steps) {
+  const bool grouped = groups_valid(P);
+  const int nv = int(P->variant_steps.size());
+  for (int pos = 0; pos < nv; ++pos) {
+    if (grouped && P->group_at[size_t(pos)] >= 0) {
+      const lf_plan::Group& g = P->groups[size_t(P->group_at[size_t(pos)])];
+      HIPCHK(launch_thin_group(reinterpret_cast<const GroupStep*>(P->ws + P->off_groups) + g.tab, g.count, g.blocks,
+                               stream));
+      pos += g.count - 1;
+      continue;
+    }
+    const int s = P->variant_steps[size_t(pos)];
     const bool tk = timed && P->hp.steps[s].kernel == P->time_kernel;
     size_t pair = 0;
     if (tk) {
@@ -567,6 +659,7 @@ void lf_plan_opts_default(lf_plan_opts* o) {
   o->mult = LF_MULT_AUTO;
   o->autotune_cache = nullptr;
   o->keep_batch_order = 0;
+  o->group_small_steps = 1;
 }
 
 const char* lf_last_error(void) { return g_err.c_str(); }
@@ -707,6 +800,8 @@ lf_status lf_plan_get_info(const lf_plan* P, lf_plan_info* out) {
   out->log2_total_macs = P->hp.log2_total_cost;
   out->workspace_bytes = P->ws_bytes;
   out->leaf_id_base = P->net.n2q + P->net.n_qubits;
+  out->n_step_groups = int32_t(P->groups.size());
+  out->n_grouped_steps = int32_t(P->group_tab.size());
   return LF_OK;
 }
 
@@ -941,6 +1036,10 @@ static lf_status ensure_ready(lf_plan* P, int64_t sigma, hipStream_t st) {
       if (r) return r;
     }
     P->invariant_done = true;
+  }
+  if (!groups_valid(P)) {
+    lf_status r = build_groups(P, st);
+    if (r) return r;
   }
   return LF_OK;
 }

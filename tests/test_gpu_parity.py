@@ -569,6 +569,34 @@ def test_batched_skinny_steps_with_gathers(lf, tmp_path):
     assert e < CHALF_TOL
 
 
+@pytest.mark.parametrize("dtype", ["c64", "chalf"])
+@pytest.mark.parametrize("launch", ["stream", "graph"])
+def test_grouped_small_steps_identical(lf, dtype, launch):
+    """Small independent streaming steps grouped into one launch give the
+    same amplitudes bit for bit as one launch per step, on the 30-qubit
+    workload (many small steps per slice), and match the oracle."""
+    if not os.path.exists(os.path.join(GOLD, "rqc30_exact.npy")):
+        pytest.skip("stored 30-qubit amplitudes not generated")
+    _say(f"grouped small steps {dtype} {launch}")
+    c, o, cb, spec = wl.standard_workload("rqc30")
+    outs = []
+    for grouped in (True, False):
+        plan = lf.Plan(c, o, cb, dtype=dtype, max_log2=spec["max_log2"], sliced_wires=wl.RQC30_SLICED_WIRES,
+                       launch=launch, slices_per_graph=8, group_small_steps=grouped).bind()
+        out = plan.contract(0, 32)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+        info = plan.info()
+        _say(f"grouped={grouped}: {info['n_step_groups']} groups of {info['n_grouped_steps']} steps")
+        if grouped:
+            assert info["n_step_groups"] > 0 and info["n_grouped_steps"] >= 2 * info["n_step_groups"]
+        else:
+            assert info["n_step_groups"] == 0
+        plan.workspace = None
+        plan.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_batch_graph_matches_sequential(lf):
     """Many subtasks of uneven shape from several circuits: one recorded
     graph with parallel lanes gives bit-identical accumulators to per-item
