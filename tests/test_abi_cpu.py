@@ -273,3 +273,17 @@ def test_batched_step_gathers_cover_closed_qubits(lib):
             assert np.array_equal(dims, dims_sorted)
         dims_sorted = dims
         p.close()
+
+
+def test_plan_info_groups_before_contraction(lib):
+    """Grouped launches are set up by the first contraction (after tuning
+    and calibration): a fresh plan reports none, with or without grouping."""
+    import paper_2406_18889_amd as lf
+    c = wl.random_circuit(3, 3, 4, seed=2)
+    o = [6, 7, 8]
+    cb = wl.closed_bitstrings(9, o, 4, seed=1)
+    for g in (True, False):
+        p = lf.Plan(c, o, cb, group_small_steps=g)
+        info = p.info()
+        assert info["n_step_groups"] == 0 and info["n_grouped_steps"] == 0
+        p.close()
