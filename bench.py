@@ -620,6 +620,8 @@ def main():
     # one tree and one slicing (slice s is the same sub-network in both)
     kw["search_dtype"] = "chalf"
     kw["keep_batch_order"] = args.keep_batch_order
+    # a traced run maps dispatches to steps by launch order: one launch per step
+    kw["group_small_steps"] = not args.trace
     plan = lf.Plan(circ, openq, cb, dtype=args.dtype, max_log2=spec["max_log2"],
                    launch=args.launch, check_overflow=False, **kw)
     info = plan.info()
