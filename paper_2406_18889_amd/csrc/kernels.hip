@@ -413,20 +413,94 @@ __global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-  // full tiles with K a multiple of BK take a copy of the loop without
-  // bounds tests (predicated loads would each be waited for)
-  auto main_loop = [&](auto full_tag) {
-    constexpr bool FULL = decltype(full_tag)::value;
-    for (int64_t k0 = 0; k0 < K; k0 += BK) {
-      // A tile: MF_BM rows x CH_ROW chunks
-      for (int c = tid; c < MF_BM * CH_ROW; c += 256) {
-        const int r = c / CH_ROW, ch = c % CH_ROW;
+  // MODE 0: whole tiles and K a multiple of BK, no bounds tests.  MODE 1: K
+  // a multiple of the 16-byte chunk, so that every chunk lies wholly inside
+  // or wholly outside the operand: one outside reads row 0, chunk 0 and is
+  // zeroed by a mask, and no load sits behind a branch (a predicated load
+  // merges its value after the branch, and the compiler then waits for
+  // every load before issuing the next).  MODE 2: K below one chunk,
+  // element by element.
+  // one K step: each thread's A chunks (NA) and B chunks (NB).  The loads
+  // of step k + 1 are issued into registers before the MFMAs of step k and
+  // stored to LDS after them, so that their latency overlaps the MFMAs and
+  // the loads of one step overlap each other.
+  constexpr int NA = MF_BM * CH_ROW / 256, NB = MF_BN * CH_ROW / 256;
+  static_assert(NA * 256 == MF_BM * CH_ROW && NB * 256 == MF_BN * CH_ROW, "chunks per thread");
+  auto put_b = [&](int r, int ch, const TI* re, const TI* im) __attribute__((always_inline)) {
+    TI row0[2 * CPC], row1[2 * CPC];
+#pragma unroll
+    for (int e = 0; e < CPC; ++e) {
+      row0[2 * e] = re[e];
+      row0[2 * e + 1] = -im[e];
+      row1[2 * e] = im[e];
+      row1[2 * e + 1] = re[e];
+    }
+    *reinterpret_cast<float4*>(&sB[(2 * r) * LDA + 2 * ch * CPC]) = *reinterpret_cast<float4*>(row0);
+    *reinterpret_cast<float4*>(&sB[(2 * r + 1) * LDA + 2 * ch * CPC]) = *reinterpret_cast<float4*>(row1);
+  };
+  auto main_loop = [&](auto mode_tag) {
+    constexpr int MODE = decltype(mode_tag)::value;
+    // raw chunks of the next step and, in MODE 1, which of them lie inside
+    // (bit i: A chunk i, bit NA + i: B chunk i); the mask is applied when
+    // the chunk is stored, so that nothing waits for the loads before then
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    v4u va[NA], vb[NB];
+    uint32_t okm = ~0u;
+    auto load_step = [&](int64_t k0) __attribute__((always_inline)) {
+      if constexpr (MODE == 1) okm = 0u;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int c = tid + 256 * i, r = c / CH_ROW, ch = c % CH_ROW;
         const int64_t kc = k0 + int64_t(ch) * CPC;
-        TI* dst = &sA[r * LDA + 2 * ch * CPC];
-        if (FULL || (r < validM && kc + CPC <= K)) {
-          *reinterpret_cast<float4*>(dst) =
-              *reinterpret_cast<const float4*>(Ab + 2 * (int64_t(r) * K + kc));
+        if constexpr (MODE == 0) {
+          va[i] = *reinterpret_cast<const v4u*>(Ab + 2 * (int64_t(r) * K + kc));
         } else {
+          const bool ok = r < validM && kc < K;
+          va[i] = *reinterpret_cast<const v4u*>(Ab + 2 * (int64_t(ok ? r : 0) * K + (ok ? kc : 0)));
+          okm |= uint32_t(ok) << i;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int c = tid + 256 * i, r = c / CH_ROW, ch = c % CH_ROW;
+        const int64_t kc = k0 + int64_t(ch) * CPC;
+        if constexpr (MODE == 0) {
+          vb[i] = *reinterpret_cast<const v4u*>(Bb + 2 * (int64_t(r) * K + kc));
+        } else {
+          const bool ok = r < validN && kc < K;
+          vb[i] = *reinterpret_cast<const v4u*>(Bb + 2 * (int64_t(ok ? r : 0) * K + (ok ? kc : 0)));
+          okm |= uint32_t(ok) << (NA + i);
+        }
+      }
+    };
+    auto keep = [&](v4u x, int bit) __attribute__((always_inline)) {
+      if constexpr (MODE == 0) return x;
+      return x & (0u - ((okm >> bit) & 1u));
+    };
+    if constexpr (MODE < 2) load_step(0);
+    for (int64_t k0 = 0; k0 < K; k0 += BK) {
+      if constexpr (MODE < 2) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+          const int c = tid + 256 * i, r = c / CH_ROW, ch = c % CH_ROW;
+          *reinterpret_cast<v4u*>(&sA[r * LDA + 2 * ch * CPC]) = keep(va[i], i);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int c = tid + 256 * i, r = c / CH_ROW, ch = c % CH_ROW;
+          const v4u x = keep(vb[i], NA + i);
+          TI tmp[2 * CPC], re[CPC], im[CPC];
+          __builtin_memcpy(tmp, &x, 16);
+#pragma unroll
+          for (int e = 0; e < CPC; ++e) { re[e] = tmp[2 * e]; im[e] = tmp[2 * e + 1]; }
+          put_b(r, ch, re, im);
+        }
+      } else {
+        // K below one chunk: element by element
+        for (int c = tid; c < MF_BM * CH_ROW; c += 256) {
+          const int r = c / CH_ROW, ch = c % CH_ROW;
+          const int64_t kc = k0 + int64_t(ch) * CPC;
+          TI* dst = &sA[r * LDA + 2 * ch * CPC];
 #pragma unroll
           for (int e = 0; e < CPC; ++e) {
             const bool ok = r < validM && kc + e < K;
@@ -434,37 +508,22 @@ __global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
             dst[2 * e + 1] = ok ? Ab[2 * (int64_t(r) * K + kc + e) + 1] : TI(0);
           }
         }
-      }
-      // B tile, expanded to B' rows 2n, 2n+1
-      for (int c = tid; c < MF_BN * CH_ROW; c += 256) {
-        const int r = c / CH_ROW, ch = c % CH_ROW;
-        const int64_t kc = k0 + int64_t(ch) * CPC;
-        TI re[CPC], im[CPC];
-        if (FULL || (r < validN && kc + CPC <= K)) {
-          TI tmp[2 * CPC];
-          *reinterpret_cast<float4*>(tmp) = *reinterpret_cast<const float4*>(Bb + 2 * (int64_t(r) * K + kc));
-#pragma unroll
-          for (int e = 0; e < CPC; ++e) { re[e] = tmp[2 * e]; im[e] = tmp[2 * e + 1]; }
-        } else {
+        for (int c = tid; c < MF_BN * CH_ROW; c += 256) {
+          const int r = c / CH_ROW, ch = c % CH_ROW;
+          const int64_t kc = k0 + int64_t(ch) * CPC;
+          TI re[CPC], im[CPC];
 #pragma unroll
           for (int e = 0; e < CPC; ++e) {
             const bool ok = r < validN && kc + e < K;
             re[e] = ok ? Bb[2 * (int64_t(r) * K + kc + e)] : TI(0);
             im[e] = ok ? Bb[2 * (int64_t(r) * K + kc + e) + 1] : TI(0);
           }
+          put_b(r, ch, re, im);
         }
-        TI row0[2 * CPC], row1[2 * CPC];
-#pragma unroll
-        for (int e = 0; e < CPC; ++e) {
-          row0[2 * e] = re[e];
-          row0[2 * e + 1] = -im[e];
-          row1[2 * e] = im[e];
-          row1[2 * e + 1] = re[e];
-        }
-        *reinterpret_cast<float4*>(&sB[(2 * r) * LDA + 2 * ch * CPC]) = *reinterpret_cast<float4*>(row0);
-        *reinterpret_cast<float4*>(&sB[(2 * r + 1) * LDA + 2 * ch * CPC]) = *reinterpret_cast<float4*>(row1);
       }
       __syncthreads();
+      if constexpr (MODE < 2)
+        if (k0 + BK < K) load_step(k0 + BK);
 #pragma unroll
       for (int kk = 0; kk < BK2; kk += Tr::KS) {
 #pragma unroll
@@ -478,9 +537,11 @@ __global__ void __launch_bounds__(256) gett_mfma(GettArgs a) {
     }
   };
   if (validM == MF_BM && validN == MF_BN && K % BK == 0)
-    main_loop(std::integral_constant<bool, true>{});
+    main_loop(std::integral_constant<int, 0>{});
+  else if (K % CPC == 0)
+    main_loop(std::integral_constant<int, 1>{});
   else
-    main_loop(std::integral_constant<bool, false>{});
+    main_loop(std::integral_constant<int, 2>{});
 
   // epilogue: lane holds column m, rows n' = 8(v/4) + 4(lane/32) + v%4
   TO* C = static_cast<TO*>(a.C);
@@ -1785,7 +1846,6 @@ __global__ void __launch_bounds__(64 * LK_WAVES) gett_longk(GettArgs a) {
   f32x16 accr, acci;
 #pragma unroll
   for (int v = 0; v < 16; ++v) { accr[v] = 0.0f; acci[v] = 0.0f; }
-  const uint4 zero4 = {0u, 0u, 0u, 0u};
   auto step = [&](uint4 ra, uint4 rb) __attribute__((always_inline)) {
     u32x4 x, re, im;
     x[0] = rb.x; x[1] = rb.y; x[2] = rb.z; x[3] = rb.w;
@@ -1801,11 +1861,22 @@ __global__ void __launch_bounds__(64 * LK_WAVES) gett_longk(GettArgs a) {
   // groups of U k steps, the loads of group g + 1 issued before the MFMAs of
   // group g (two register sets), so that two groups are in flight
   uint4 ra[2][U], rb[2][U];
+  // rows past M (N) read row 0 and are zeroed by a mask: whole 16-byte
+  // loads with no branch around them (a conditional load here became four
+  // 4-byte loads, each behind its own branch)
+  const uint32_t mA = okA ? ~0u : 0u, mB = okB ? ~0u : 0u;
+  auto masked = [](uint4 x, uint32_t m) __attribute__((always_inline)) {
+    x.x &= m;
+    x.y &= m;
+    x.z &= m;
+    x.w &= m;
+    return x;
+  };
   auto load = [&](int set, int64_t t) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ra[set][u] = okA ? pa[2 * (t + u) + half] : zero4;
-      rb[set][u] = okB ? pb[2 * (t + u) + half] : zero4;
+      ra[set][u] = masked(pa[2 * (t + u) + half], mA);
+      rb[set][u] = masked(pb[2 * (t + u) + half], mB);
     }
   };
   const int64_t groups = per / U;
@@ -1821,7 +1892,7 @@ __global__ void __launch_bounds__(64 * LK_WAVES) gett_longk(GettArgs a) {
     }
   }
   for (int64_t t = t0 + groups * U; t < t1; ++t)
-    step(okA ? pa[2 * t + half] : zero4, okB ? pb[2 * t + half] : zero4);
+    step(masked(pa[2 * t + half], mA), masked(pb[2 * t + half], mB));
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     red[w][v][lane] = accr[v];
