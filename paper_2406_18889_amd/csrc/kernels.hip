@@ -30,10 +30,20 @@ typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 constexpr float HALF_MAX = 65504.0f;
 
-__device__ __forceinline__ int64_t scatter_bits(int64_t v, const int64_t* st, int nb) {
+template <int NS>
+__device__ __forceinline__ int64_t scatter_bits(int64_t v, const int64_t (&st)[NS], int nb) {
+  // branch-free, eight bits a round: the eight strides of a round are loaded
+  // together (one wait) and masked by their bits; bits of v at or above nb
+  // are dropped, so the strides read past nb (inside the array) add nothing.
+  // (With a branch per bit, each stride's load from the kernel arguments
+  // was waited for on its own: one memory latency per bit of every offset.)
+  static_assert(NS % 8 == 0, "whole rounds stay inside the array");
+  v &= (int64_t(1) << nb) - 1;
   int64_t s = 0;
-  for (int b = 0; b < nb; ++b)
-    if ((v >> b) & 1) s += st[b];
+  for (int b = 0; b < nb; b += 8) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += st[b + i] & -((v >> (b + i)) & 1);
+  }
   return s;
 }
 
