@@ -284,10 +284,14 @@ __global__ void __launch_bounds__(256) gett_narrow(GettArgs a) {
   TO* C = static_cast<TO*>(a.C);
   float lmax = 0.0f;
   unsigned lsat = 0;
+  // row j of this thread is mb + 256 j + tid (M >= 256 and, with RPT > 1,
+  // a multiple of 256 RPT): its low 8 bits are the thread's and the rest
+  // is the same in every lane, so that part of its offset is scalar work
+  const int64_t mb = r0 & (M - 1);
+  const int64_t lo = scatter_bits(int64_t(threadIdx.x), a.cm, 8);
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int64_t m = (r0 + threadIdx.x + 256 * j) & (M - 1);
-    const int64_t cbase = czv + scatter_bits(m, a.cm, a.nm);
+    const int64_t cbase = czv + lo + scatter_bits(mb + 256 * j, a.cm, a.nm);
     for (int n = 0; n < N; ++n) {
       float cr = 0.f, ci = 0.f;
 #pragma unroll
