@@ -287,11 +287,17 @@ __global__ void __launch_bounds__(256) gett_narrow(GettArgs a) {
   // row j of this thread is mb + 256 j + tid (M >= 256 and, with RPT > 1,
   // a multiple of 256 RPT): its low 8 bits are the thread's and the rest
   // is the same in every lane, so that part of its offset is scalar work
+  // (mb has no bits below bit 8 + log2 RPT, so 256 j adds its strides bit
+  // by bit)
   const int64_t mb = r0 & (M - 1);
   const int64_t lo = scatter_bits(int64_t(threadIdx.x), a.cm, 8);
+  const int64_t hi = czv + lo + scatter_bits(mb, a.cm, a.nm);
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int64_t cbase = czv + lo + scatter_bits(mb + 256 * j, a.cm, a.nm);
+    int64_t cbase = hi;
+#pragma unroll
+    for (int b = 0; (1 << b) < RPT; ++b)
+      if ((j >> b) & 1) cbase += a.cm[8 + b];
     for (int n = 0; n < N; ++n) {
       float cr = 0.f, ci = 0.f;
 #pragma unroll
